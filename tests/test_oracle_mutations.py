@@ -1,0 +1,64 @@
+"""The pins catch plausible mistakes: each test here compiles a copy of the
+oracle with one planted error (on the CPU) and checks that at least one pin
+of ``test_oracle_pins`` fails against it."""
+import os
+
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "jefi_oracle.c")
+
+MUTATIONS = {
+    "E: sign of the -Jdot/R term": ("- Jd[a] * iR)", "+ Jd[a] * iR)"),
+    "B: overall sign": ("orc_nadd(&acc[3 + a], -(cJ[a] * iR3 + cD[a] * iR2))",
+                        "orc_nadd(&acc[3 + a], (cJ[a] * iR3 + cD[a] * iR2))"),
+    "cross product transposed": ("double cJ[3] = {d[1] * J[2] - d[2] * J[1], d[2] * J[0] - d[0] * J[2], d[0] * J[1] - d[1] * J[0]};",
+                                 "double cJ[3] = {d[2] * J[1] - d[1] * J[2], d[0] * J[2] - d[2] * J[0], d[1] * J[0] - d[0] * J[1]};"),
+    "volume element dropped": ("const double pref = (src->spacing[0] * src->spacing[1] * src->spacing[2]) / (4.0 * M_PI);",
+                               "const double pref = 1.0 / (4.0 * M_PI);"),
+    "prefactor 1/(2 pi)": ("/ (4.0 * M_PI);", "/ (2.0 * M_PI);"),
+    "rho_dot weighted by 1/R^3": ("d[a] * rhod * iR2", "d[a] * rhod * iR3"),
+    "derivative of the interpolant": ("double d0 = (h0 - hm) * inv_dt;",
+                                      "double d0 = (orc_h(hist, ns, k + 1, ch, s) - h0) * inv_dt;"),
+    "slice index one late": ("*k = tm->a_i + (int64_t)m;", "*k = tm->a_i + (int64_t)m + 1;"),
+    "weight f complemented": ("*f = u - m;", "*f = 1.0 - (u - m);"),
+    "past held at the oldest slice": ("if (j < 0) return 0.0;", "if (j < 0) j = 0;"),
+    "retarded time uses R*c*dt": ("out->inv_cdt = 1.0 / (c * dt);", "out->inv_cdt = c / dt;"),
+    "Jdot missing from B": ("-(cJ[a] * iR3 + cD[a] * iR2)", "-(cJ[a] * iR3)"),
+}
+
+PIN_CALLS = [
+    pins.test_static_cell_is_coulomb_and_biot_savart,
+    pins.test_linear_history_is_reproduced_exactly,
+    pins.test_quadratic_history_pins_the_derivative_reading,
+    lambda: pins.test_switch_on_at_the_oldest_slice("k=-1"),
+    lambda: pins.test_switch_on_at_the_oldest_slice("k=0"),
+    pins.test_gauss_flux_equals_enclosed_charge_and_B_flux_vanishes,
+    pins.test_current_ring_on_axis,
+    pins.test_exact_integer_retarded_positions,
+    pins.test_saturation_for_constant_sources,
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTATIONS[name]
+    text = open(SRC).read()
+    assert text.count(old) >= 1, f"mutation anchor not found: {old}"
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(text.replace(old, new))
+    lib = str(tmp_path / "libmutant.so")
+    oracle.build(source=str(mutated), target=lib)
+    failures = 0
+    oracle._use_library(lib)
+    try:
+        for call in PIN_CALLS:
+            try:
+                call()
+            except (AssertionError, ValueError):
+                failures += 1
+    finally:
+        oracle._use_library(None)
+    assert failures >= 1, f"no pin caught: {name}"
