@@ -1,0 +1,170 @@
+/*
+ * libjefi -- evaluation of the discretised Jefimenko equations on gfx950.
+ *
+ * For every observation point r of a uniform grid at time t the library sums,
+ * over every cell r' of a uniform source grid, the charge density rho and the
+ * current density J and their backward-difference time derivatives, read at
+ * the retarded time t_r = t - |r - r'|/c from a stored history of source
+ * slices, weighted by the 1/R^3, 1/R^2 and 1/R kernels, and returns E and B
+ * (paper: section "GPU implementation of Jefimenko's equations", the
+ * discretised equations for E, B and t_r; units: rationalised
+ * Lorentz-Heaviside, section "Jefimenko's equations").
+ *
+ *   E(r,t) =  1/(4 pi) sum [ d rho/R^3 + d rho_dot/R^2 - J_dot/R ] dOmega
+ *   B(r,t) = -1/(4 pi) sum [ d x J/R^3 + d x J_dot/R^2 ] dOmega
+ *
+ * Conventions shared by every entry point:
+ *   - A grid's cell (i,j,k) has its centre at origin + (i,j,k)*spacing
+ *     (evaluated in FP64 as a multiply then an add); linear cell index
+ *     i + n0*(j + n1*k) (x fastest).  dOmega is the source cell volume.
+ *   - History step s sits at time t0 + s*dt.  An evaluation with nt slices
+ *     uses steps newest-nt+1 .. newest.  Between slices values are linear in
+ *     time; the derivative is the same linear interpolation of the
+ *     slice-wise backward differences (h_k - h_(k-1))/dt.  Slices before the
+ *     oldest used step count as zero.
+ *   - Slice index: with a = (t - t0)/dt - (newest - nt + 1) split as
+ *     a = a_i + a_f (a_i = floor(a)) on the host in FP64, each pair uses
+ *     k = a_i + floor(u), f = u - floor(u), u = a_f - R/(c dt), where
+ *     R = sqrt((dx*dx + dy*dy) + dz*dz) of d = r - r' -- all FP64 without
+ *     contraction.  This decision is bit-exact in both precisions.
+ *   - Coarse screening: a pair with |dx| <= s_x, |dy| <= s_y, |dz| <= s_z
+ *     (and any pair with R == 0) contributes nothing.
+ *   - Device pointers are HIP device memory on the current device; the
+ *     library never frees caller memory.  `stream` is a hipStream_t passed as
+ *     void* (NULL = the null stream).  Calls are stream-ordered and
+ *     asynchronous: outputs are valid once the stream reaches the call.
+ *   - Every function returns jefi_status; on an error nothing is written to
+ *     the outputs and jefi_last_error() explains (thread-local text).
+ *     JEFI_EDEVICE after a HIP failure is sticky for the process.
+ */
+#ifndef LIBJEFI_H
+#define LIBJEFI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  JEFI_OK = 0,
+  JEFI_PENDING = 1,      /* server request not finished yet */
+  JEFI_EINVAL = -1,      /* bad argument or descriptor */
+  JEFI_ENOMEM = -2,      /* device allocation failed */
+  JEFI_EDEVICE = -3,     /* a HIP call failed (sticky) */
+  JEFI_EBUSY = -4,       /* server queue full: retry */
+  JEFI_ENOENT = -5,      /* unknown ticket or session */
+  JEFI_ETOOLARGE = -6    /* can never fit the memory budget */
+} jefi_status;
+
+typedef enum { JEFI_F32 = 0, JEFI_F64 = 1 } jefi_dtype;
+
+/* JEFI_PREC_F64: all pair arithmetic in FP64 (needs an F64 history).
+ * JEFI_PREC_F32_COMP: FP32 pair arithmetic (rsqrt, FMA) with compensated
+ * accumulation, FP64 for the slice index near slice boundaries and for the
+ * final per-point reduction (needs an F32 history). */
+typedef enum { JEFI_PREC_F64 = 0, JEFI_PREC_F32_COMP = 1 } jefi_precision;
+
+/* Uniform grid: n cells per axis (n >= 1 each, or all three 0 for an empty
+ * grid), centre of cell 0 and spacing (spacing > 0, finite). */
+typedef struct {
+  int32_t n[3];
+  double origin[3];
+  double spacing[3];
+} jefi_grid;
+
+/* Resident source history: a ring of `capacity` slices in DEVICE memory.
+ * Slot layout (the library's, written by jefi_history_push): per slot,
+ * bricks of 2x2x2 source cells in brick order bx + nbx*(by + nby*bz)
+ * (nbx = ceil(n0/2) ...), inside a brick cell cx + 2*cy + 4*cz, and per cell
+ * the 4 channels rho, Jx, Jy, Jz contiguous in `dtype`; cells beyond the grid
+ * edge are zero.  Step s lives in slot s % capacity.  `newest` is the
+ * absolute step of the newest pushed slice (-1 = none), `t0` the time of
+ * step 0.  The caller owns `data` (jefi_history_bytes() bytes). */
+typedef struct {
+  void* data;
+  int32_t dtype;       /* jefi_dtype */
+  int32_t capacity;
+  int64_t newest;
+  double t0;
+} jefi_history;
+
+/* Output fields in DEVICE memory: E and B each [3][n_obs] of `dtype`,
+ * component-major (x, y, z), points in linear order. */
+typedef struct {
+  void* E;
+  void* B;
+  int32_t dtype;       /* jefi_dtype */
+} jefi_fields;
+
+typedef struct {
+  double c;              /* speed of light, > 0 (default 1) */
+  double screen[3];      /* screening half-widths, used when screen_set != 0 */
+  int32_t screen_set;    /* 0: half the source spacing per axis (default) */
+  int32_t precision;     /* jefi_precision (default JEFI_PREC_F32_COMP) */
+  uint32_t flags;        /* reserved, 0 */
+  int32_t tile_config;   /* 0 = automatic; >0 selects a tuned launch shape */
+} jefi_options;
+
+const char* jefi_version(void);
+const char* jefi_last_error(void);
+void jefi_options_default(jefi_options* opt);
+
+/* ---- source history (row: history ingest) ------------------------------
+ * The stored history of rho and J slices the sums read at retarded times
+ * (paper, section "Parameter dependence": rho and J are kept in GPU memory
+ * for all relevant times and are not released between calls). */
+
+/* Bytes of a ring of `capacity` slices for `src` in `dtype`; 0 on bad input. */
+uint64_t jefi_history_bytes(const jefi_grid* src, int32_t capacity, int32_t dtype);
+
+/* Fill in `h` for a caller-owned device buffer of `bytes` bytes and zero it
+ * (stream-ordered).  newest = -1.  EINVAL on a short buffer or bad sizes. */
+jefi_status jefi_history_init(jefi_history* h, void* data, uint64_t bytes, const jefi_grid* src,
+                              int32_t capacity, int32_t dtype, double t0, void* stream);
+
+/* Append one slice: `slice` is DEVICE memory [4][n_src] of h->dtype in linear
+ * cell order (channel 0 = rho, 1..3 = Jx, Jy, Jz).  It becomes step
+ * h->newest + 1 (written to its slot in the library layout, overwriting the
+ * oldest step once the ring is full); h->newest is incremented on return. */
+jefi_status jefi_history_push(jefi_history* h, const jefi_grid* src, const void* slice,
+                              void* stream);
+
+/* ---- field evaluation (rows: host prelude, pair loop, tile staging,
+ * reduction/epilogue) -------------------------------------------------------
+ * E and B at time t on the observation grid from the last `nt` steps of the
+ * history (1 <= nt <= min(capacity, newest + 1)); t must not lie after the
+ * newest step (beyond FP64 rounding of t): EINVAL otherwise.  `opt` NULL =
+ * defaults.  The history dtype must match the precision (F32 for
+ * F32_COMP, F64 for F64); `out->dtype` may be either.  An empty observation
+ * grid is a no-op; an empty source grid gives zero fields. */
+jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt,
+                             const jefi_grid* obs, double t, const jefi_fields* out,
+                             const jefi_options* opt, void* stream);
+
+/* ---- slice-decision diagnostics ------------------------------------------
+ * The integer decisions the field kernels take, exposed for bit-exact
+ * checks against an independent implementation. */
+
+/* Per-pair decision of the device index code, DEVICE int32 out[n_obs][n_src]:
+ * INT32_MIN = screened (or R == 0), -2 = stencil wholly before the oldest
+ * slice (k < -1), else k in [-1, nt-1].  `precision` picks the FP32 guarded
+ * or the FP64 device sequence.  For small problems (n_obs*n_src <= 2^31). */
+jefi_status jefi_slice_index_dump(const jefi_grid* src, int32_t nt, double dt, int64_t newest,
+                                  double t0, const jefi_grid* obs, double t,
+                                  const jefi_options* opt, int32_t* out, void* stream);
+
+/* Per-observation-point fingerprint computed by the field kernel's own path
+ * (same tiling, staging windows, culling and index code), DEVICE int64
+ * fp[n_obs][4]: number of pairs that are neither screened nor wholly before
+ * the oldest slice, the sum of their k, the sum of k*(s+1) (wrapping, s =
+ * linear source index), and the number of screened pairs met. */
+jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* hist, double dt,
+                                   int32_t nt, const jefi_grid* obs, double t,
+                                   const jefi_options* opt, int64_t* fp, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBJEFI_H */

@@ -1,0 +1,218 @@
+"""Python binding of libjefi (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library ``libjefi.so`` built from
+``csrc/``; this module only converts grids, torch device tensors and streams
+to the C ABI declared in ``include/libjefi.h`` and raises ``JefiError`` on a
+failed status.  Importing it without a built library raises immediately:
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjefi.so")
+
+JEFI_OK, JEFI_PENDING = 0, 1
+JEFI_EINVAL, JEFI_ENOMEM, JEFI_EDEVICE, JEFI_EBUSY, JEFI_ENOENT, JEFI_ETOOLARGE = -1, -2, -3, -4, -5, -6
+JEFI_F32, JEFI_F64 = 0, 1
+JEFI_PREC_F64, JEFI_PREC_F32_COMP = 0, 1
+INT32_MIN = -(2 ** 31)
+
+STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY",
+                -5: "ENOENT", -6: "ETOOLARGE"}
+
+# Every function the header declares (the CPU tests check the exports).
+EXPORTS = [
+    "jefi_version", "jefi_last_error", "jefi_options_default", "jefi_history_bytes",
+    "jefi_history_init", "jefi_history_push", "jefi_eval_fields", "jefi_slice_index_dump",
+    "jefi_slice_fingerprint",
+]
+
+
+class JefiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class jefi_grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("origin", C.c_double * 3), ("spacing", C.c_double * 3)]
+
+
+class jefi_history(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("dtype", C.c_int32), ("capacity", C.c_int32),
+                ("newest", C.c_int64), ("t0", C.c_double)]
+
+
+class jefi_fields(C.Structure):
+    _fields_ = [("E", C.c_void_p), ("B", C.c_void_p), ("dtype", C.c_int32)]
+
+
+class jefi_options(C.Structure):
+    _fields_ = [("c", C.c_double), ("screen", C.c_double * 3), ("screen_set", C.c_int32),
+                ("precision", C.c_int32), ("flags", C.c_uint32), ("tile_config", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
+                          f"python {os.path.join(_HERE, 'build.py')}")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp = C.c_void_p
+    sig = {
+        "jefi_version": ([], C.c_char_p),
+        "jefi_last_error": ([], C.c_char_p),
+        "jefi_options_default": ([P(jefi_options)], None),
+        "jefi_history_bytes": ([P(jefi_grid), C.c_int32, C.c_int32], C.c_uint64),
+        "jefi_history_init": ([P(jefi_history), vp, C.c_uint64, P(jefi_grid), C.c_int32, C.c_int32,
+                               C.c_double, vp], C.c_int),
+        "jefi_history_push": ([P(jefi_history), P(jefi_grid), vp, vp], C.c_int),
+        "jefi_eval_fields": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32, P(jefi_grid),
+                              C.c_double, P(jefi_fields), P(jefi_options), vp], C.c_int),
+        "jefi_slice_index_dump": ([P(jefi_grid), C.c_int32, C.c_double, C.c_int64, C.c_double,
+                                   P(jefi_grid), C.c_double, P(jefi_options), vp, vp], C.c_int),
+        "jefi_slice_fingerprint": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32,
+                                    P(jefi_grid), C.c_double, P(jefi_options), vp, vp], C.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(st: int):
+    if st != JEFI_OK:
+        raise JefiError(st, lib.jefi_last_error().decode())
+
+
+def make_grid(g) -> jefi_grid:
+    """A jefi_grid from anything with ``n``, ``origin`` and ``spacing``."""
+    out = jefi_grid()
+    for a in range(3):
+        out.n[a] = int(g.n[a])
+        out.origin[a] = float(g.origin[a])
+        out.spacing[a] = float(g.spacing[a])
+    return out
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+def jefi_version() -> str:
+    return lib.jefi_version().decode()
+
+
+def jefi_last_error() -> str:
+    return lib.jefi_last_error().decode()
+
+
+def jefi_options_default(precision: Optional[int] = None, c: Optional[float] = None,
+                         screen: Optional[Sequence[float]] = None) -> jefi_options:
+    opt = jefi_options()
+    lib.jefi_options_default(C.byref(opt))
+    if precision is not None:
+        opt.precision = int(precision)
+    if c is not None:
+        opt.c = float(c)
+    if screen is not None:
+        opt.screen_set = 1
+        for a in range(3):
+            opt.screen[a] = float(screen[a])
+    return opt
+
+
+def jefi_history_bytes(src, capacity: int, dtype: int) -> int:
+    return int(lib.jefi_history_bytes(C.byref(make_grid(src)), int(capacity), int(dtype)))
+
+
+def jefi_history_init(data, src, capacity: int, dtype: int, t0: float = 0.0,
+                      stream=None) -> jefi_history:
+    """``data``: a contiguous device tensor of at least jefi_history_bytes() bytes
+    (the caller keeps it alive as long as the history is used)."""
+    h = jefi_history()
+    nbytes = data.numel() * data.element_size()
+    _check(lib.jefi_history_init(C.byref(h), _ptr(data), nbytes, C.byref(make_grid(src)),
+                                 int(capacity), int(dtype), float(t0), _stream_ptr(stream)))
+    return h
+
+
+def jefi_history_push(h: jefi_history, src, slice_, stream=None) -> None:
+    """``slice_``: device tensor [4][n_src] of the history dtype."""
+    _check(lib.jefi_history_push(C.byref(h), C.byref(make_grid(src)), _ptr(slice_),
+                                 _stream_ptr(stream)))
+
+
+def jefi_eval_fields(src, h: jefi_history, dt: float, nt: int, obs, t: float, E, B,
+                     opt: Optional[jefi_options] = None, stream=None) -> None:
+    """E, B: device tensors [3][n_obs] (float32 or float64)."""
+    import torch
+    dt_out = JEFI_F64 if E.dtype == torch.float64 else JEFI_F32
+    if B.dtype != E.dtype:
+        raise ValueError("E and B must share a dtype")
+    f = jefi_fields(_ptr(E), _ptr(B), dt_out)
+    _check(lib.jefi_eval_fields(C.byref(make_grid(src)), C.byref(h), float(dt), int(nt),
+                                C.byref(make_grid(obs)), float(t), C.byref(f),
+                                C.byref(opt) if opt is not None else None, _stream_ptr(stream)))
+
+
+def jefi_slice_index_dump(src, nt: int, dt: float, newest: int, t0: float, obs, t: float, out,
+                          opt: Optional[jefi_options] = None, stream=None) -> None:
+    """out: device int32 tensor [n_obs][n_src]."""
+    _check(lib.jefi_slice_index_dump(C.byref(make_grid(src)), int(nt), float(dt), int(newest),
+                                     float(t0), C.byref(make_grid(obs)), float(t),
+                                     C.byref(opt) if opt is not None else None, _ptr(out),
+                                     _stream_ptr(stream)))
+
+
+def jefi_slice_fingerprint(src, h: jefi_history, dt: float, nt: int, obs, t: float, fp,
+                           opt: Optional[jefi_options] = None, stream=None) -> None:
+    """fp: device int64 tensor [n_obs][4]."""
+    _check(lib.jefi_slice_fingerprint(C.byref(make_grid(src)), C.byref(h), float(dt), int(nt),
+                                      C.byref(make_grid(obs)), float(t),
+                                      C.byref(opt) if opt is not None else None, _ptr(fp),
+                                      _stream_ptr(stream)))
+
+
+def upload_history(src, hist_np, dtype: int, t0: float = 0.0, newest: Optional[int] = None,
+                   capacity: Optional[int] = None, device: str = "cuda", stream=None):
+    """Push the slices ``hist_np[nt][4][n_src]`` (oldest first) into a fresh
+    ring; returns (storage tensor, jefi_history).  When ``newest`` is given
+    the first slice becomes step newest - nt + 1."""
+    import torch
+    nt = int(hist_np.shape[0])
+    capacity = int(capacity or nt)
+    nbytes = jefi_history_bytes(src, capacity, dtype)
+    store = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=device)
+    h = jefi_history_init(store, src, capacity, dtype, t0, stream)
+    if newest is not None:
+        h.newest = int(newest) - nt
+    tdt = torch.float64 if dtype == JEFI_F64 else torch.float32
+    for j in range(nt):
+        sl = torch.as_tensor(hist_np[j], dtype=tdt).to(device).contiguous()
+        jefi_history_push(h, src, sl, stream)
+    return store, h

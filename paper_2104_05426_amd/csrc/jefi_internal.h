@@ -1,0 +1,88 @@
+// Internal definitions shared by the host layer (jefi_api.cpp) and the
+// kernels (jefi_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace jefi {
+
+// Source bricks: 2x2x2 cells, the unit of the ring layout and of staging.
+constexpr int kBrickCells = 8;
+// Observation tile: 8x8x8 points per workgroup, 4x4x4 per wavefront.
+constexpr int kTileEdge = 8;
+constexpr int kThreads = 512;
+// Slice-window slots staged per source cell and launch variant.
+constexpr int kWmax = 32;
+
+struct GridD {
+  int n[3];
+  double o[3];
+  double h[3];
+};
+
+// Everything a pair-kernel launch needs; passed by value.
+struct PairParams {
+  GridD src, obs;
+  int nbx, nby, nbz;
+  int n_bricks;
+  int ntx, nty, ntz;
+  int n_tiles;
+  int n_splits;
+  int bricks_per_split;
+  int n_wg;
+  // time axis (logical slice units, oldest used slice = 0)
+  int a_i;
+  double a_f;
+  double inv_cdt;
+  double inv_dt;
+  int nt;
+  int capacity;
+  int slot_base;         // (newest - nt + 1) mod capacity
+  double screen[3];
+  double margin;         // slack on box-derived slice bounds, slice units
+  double near_slack;     // slack on the box screening test, length units
+  float guard;           // FP32 index guard half-width, slice units
+  const void* ring;      // device ring, library layout
+  long long slot_elems;  // elements (of the ring dtype) per slot
+  double* partial;       // FP64 [n_splits][6][n_obs] (unscaled sums)
+  void* E;
+  void* B;
+  int out_f64;
+  double pref;           // dOmega / (4 pi)
+  unsigned long long* fp;  // fingerprint output [n_obs][4]
+  int direct;            // 1: one split, the pair kernel writes E/B itself
+};
+
+struct EpilogueParams {
+  const double* partial;
+  int n_splits;
+  long long n_obs;
+  double pref;
+  void* E;
+  void* B;
+  int out_f64;
+};
+
+struct DumpParams {
+  GridD src, obs;
+  int a_i;
+  double a_f;
+  double inv_cdt;
+  double screen[3];
+  float guard;
+  int use_f64;
+  int* out;
+};
+
+// Launchers (jefi_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_zero(void* p, unsigned long long bytes, hipStream_t s);
+hipError_t launch_ingest(const void* slice, void* slot, const GridD& src, int nbx, int nby,
+                         int is_f64, hipStream_t s);
+hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk,
+                        hipStream_t s);
+hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);
+hipError_t launch_fill_zero_fields(void* E, void* B, long long n_obs, int out_f64, hipStream_t s);
+hipError_t launch_dump(const DumpParams& p, hipStream_t s);
+
+}  // namespace jefi

@@ -1,0 +1,690 @@
+// gfx950 kernels for the discretised Jefimenko sums.
+//
+// Built with -ffp-contract=off: every FMA in this file is written out
+// explicitly, so the canonical FP64 slice-index sequence (coordinates as
+// origin + index*spacing, R = sqrt((dx*dx + dy*dy) + dz*dz), u = a_f - R/(c dt))
+// is evaluated exactly as specified.
+//
+// Pair kernel design (one workgroup = one 8x8x8 observation tile x one range
+// of source bricks):
+//   * each lane owns one observation point; a wavefront covers a compact
+//     4x4x4 block so neighbouring lanes read neighbouring history slices;
+//   * source cells come in 2x2x2 bricks; per round a workgroup computes, for
+//     G bricks, the window of slices [wlo, whi] its tile can reach (from the
+//     FP64 min/max tile-brick distances), skips bricks whose whole window is
+//     before the oldest slice, and stages the window into LDS as four planes
+//     h_k, S_k = h_(k+1) - h_k, D_k = (h_k - h_(k-1))/dt and T_k = D_(k+1) - D_k
+//     so that value and backward difference at the retarded time are one FMA
+//     each: v = h_k + f S_k, v_dot = D_k + f T_k;
+//   * the FP32 path computes R with rsqrt and the slice index in FP32; when
+//     the fractional position lies within the proven error band of a slice
+//     boundary it recomputes the canonical FP64 sequence, so the index is
+//     identical to the FP64 decision;
+//   * screening is tested per pair (canonical FP64) only in bricks whose box
+//     comes within the screening width of the tile box;
+//   * FP32 per-round partial sums feed compensated (two-sum) FP32 running
+//     totals; the per-point totals are reduced in FP64 across splits by the
+//     epilogue in a fixed order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "jefi_internal.h"
+
+namespace jefi {
+namespace {
+
+__device__ __forceinline__ double canon(double o, int i, double h) { return o + (double)i * h; }
+
+// Canonical FP64 position of the retarded time in slice units relative to
+// a_i, from the canonical separation d.
+__device__ __forceinline__ double canon_u(double dx, double dy, double dz, double af, double icdt) {
+  double r2 = (dx * dx + dy * dy) + dz * dz;
+  double R = __builtin_sqrt(r2);
+  return af - R * icdt;
+}
+
+__device__ __forceinline__ bool canon_screened(double dx, double dy, double dz, const double* s) {
+  if (__builtin_fabs(dx) <= s[0] && __builtin_fabs(dy) <= s[1] && __builtin_fabs(dz) <= s[2])
+    return true;
+  double r2 = (dx * dx + dy * dy) + dz * dz;
+  return __builtin_sqrt(r2) == 0.0;
+}
+
+// Map the hardware workgroup id so that consecutive logical ids land on the
+// same XCD (workgroups are dealt round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  int q = n >> 3, r = n & 7;
+  int x = bid & 7, l = bid >> 3;
+  return x * q + min(x, r) + l;
+}
+
+// FP32 slice decision with the FP64 fallback near slice boundaries.
+// Returns floor(u) (clamped below at -1e9) and the weight f.
+template <class Canon>
+__device__ __forceinline__ void index_f32(float dx, float dy, float dz, float af, float icdt,
+                                          float halfg, Canon canon_fn, float& m, float& f,
+                                          float& ri) {
+  float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+  ri = __builtin_amdgcn_rsqf(r2);
+  float R = r2 * ri;
+  float u = __builtin_fmaf(-R, icdt, af);
+  float fl = __builtin_floorf(u);
+  float fr = u - fl;
+  if (__builtin_expect(__builtin_fabsf(fr - 0.5f) > halfg, 0)) {
+    double u64 = canon_fn();
+    double m64 = __builtin_floor(u64);
+    fl = (float)__builtin_fmax(m64, -1e9);
+    fr = (float)(u64 - m64);
+  }
+  m = __builtin_fmaxf(fl, -1e9f);
+  f = fr;
+}
+
+template <typename T>
+struct Traits;
+template <>
+struct Traits<float> {
+  static constexpr int kPlanes = 4;  // h, S, D, T; each float4 (rho, Jx, Jy, Jz)
+};
+template <>
+struct Traits<double> {
+  static constexpr int kPlanes = 8;  // (h.rho,h.Jx),(h.Jy,h.Jz),(S..),(S..),(D..),(D..),(T..),(T..)
+};
+
+__device__ __forceinline__ void two_sum_acc(float& s, float& c, float x) {
+  float t = s + x;
+  float bp = t - s;
+  float e = (s - (t - bp)) + (x - bp);
+  s = t;
+  c += e;
+}
+
+// Four channels of one cell at logical slice j (zero outside 0..nt-1).
+__device__ __forceinline__ float4 ring4(const float* ring, const PairParams& p, int j, int b, int c) {
+  if (j < 0 || j > p.nt - 1) return make_float4(0.f, 0.f, 0.f, 0.f);
+  int slot = p.slot_base + j;
+  if (slot >= p.capacity) slot -= p.capacity;
+  return *(const float4*)(ring + (long long)slot * p.slot_elems + ((long long)b * kBrickCells + c) * 4);
+}
+
+__device__ __forceinline__ void ring4(const double* ring, const PairParams& p, int j, int b, int c,
+                                      double out[4]) {
+  if (j < 0 || j > p.nt - 1) {
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    return;
+  }
+  int slot = p.slot_base + j;
+  if (slot >= p.capacity) slot -= p.capacity;
+  const double2* q =
+      (const double2*)(ring + (long long)slot * p.slot_elems + ((long long)b * kBrickCells + c) * 4);
+  const double2 lo = q[0], hi = q[1];
+  out[0] = lo.x; out[1] = lo.y; out[2] = hi.x; out[3] = hi.y;
+}
+
+// Brick table entry computed by one thread per brick and round.
+struct BrickInfo {
+  int wlo, whi, flags, b;  // flags: bit0 dead, bit1 near, bits 8..15 valid-cell mask
+};
+
+template <typename T, int G, bool FP, bool MULTI>
+__global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
+  constexpr int NPL = Traits<T>::kPlanes;
+  constexpr int CELLS = G * kBrickCells;
+  constexpr int PU = CELLS * kWmax;  // 16-byte units per plane
+  __shared__ float4 lds[NPL * PU];
+  __shared__ int4 tab_i[G];
+  __shared__ float4 tab_f[G];
+  __shared__ double tab_c[G][6];
+
+  const int bid = xcd_remap((int)blockIdx.x, p.n_wg);
+  const int split = bid / p.n_tiles;
+  const int tile = bid - split * p.n_tiles;
+  const int tx = tile % p.ntx;
+  const int ty = (tile / p.ntx) % p.nty;
+  const int tz = tile / (p.ntx * p.nty);
+  const int ix0 = tx * kTileEdge, iy0 = ty * kTileEdge, iz0 = tz * kTileEdge;
+  const int ix1 = min(ix0 + kTileEdge - 1, p.obs.n[0] - 1);
+  const int iy1 = min(iy0 + kTileEdge - 1, p.obs.n[1] - 1);
+  const int iz1 = min(iz0 + kTileEdge - 1, p.obs.n[2] - 1);
+  const int t = (int)threadIdx.x;
+  const int w = t >> 6, l = t & 63;
+  const int ix = ix0 + (w & 1) * 4 + (l & 3);
+  const int iy = iy0 + ((w >> 1) & 1) * 4 + ((l >> 2) & 3);
+  const int iz = iz0 + (w >> 2) * 4 + (l >> 4);
+  const bool valid = ix <= ix1 && iy <= iy1 && iz <= iz1;
+  const int cix = min(ix, ix1), ciy = min(iy, iy1), ciz = min(iz, iz1);
+
+  const double refx = canon(p.obs.o[0], ix0, p.obs.h[0]);
+  const double refy = canon(p.obs.o[1], iy0, p.obs.h[1]);
+  const double refz = canon(p.obs.o[2], iz0, p.obs.h[2]);
+  const double thix = canon(p.obs.o[0], ix1, p.obs.h[0]);
+  const double thiy = canon(p.obs.o[1], iy1, p.obs.h[1]);
+  const double thiz = canon(p.obs.o[2], iz1, p.obs.h[2]);
+  const double rox = canon(p.obs.o[0], cix, p.obs.h[0]);
+  const double roy = canon(p.obs.o[1], ciy, p.obs.h[1]);
+  const double roz = canon(p.obs.o[2], ciz, p.obs.h[2]);
+
+  const T* ring = (const T*)p.ring;
+  const int b_begin = split * p.bricks_per_split;
+  const int b_end = min(b_begin + p.bricks_per_split, p.n_bricks);
+
+  // accumulators
+  float sE[3] = {0.f, 0.f, 0.f}, cE[3] = {0.f, 0.f, 0.f};
+  float sB[3] = {0.f, 0.f, 0.f}, cB[3] = {0.f, 0.f, 0.f};
+  double dE[3] = {0.0, 0.0, 0.0}, dB[3] = {0.0, 0.0, 0.0};
+  unsigned long long n_live = 0, sum_k = 0, sum_kw = 0, n_scr = 0;
+
+  const float xo = (float)(rox - refx), yo = (float)(roy - refy), zo = (float)(roz - refz);
+  const float hsx = (float)p.src.h[0], hsy = (float)p.src.h[1], hsz = (float)p.src.h[2];
+  const float af32 = (float)p.a_f, icdt32 = (float)p.inv_cdt, halfg = 0.5f - p.guard;
+  const T inv_dt = (T)p.inv_dt;
+
+  for (int rb = b_begin; rb < b_end; rb += G) {
+    __syncthreads();  // the previous round's readers are done with LDS and the table
+    if (t < G) {
+      const int b = rb + t;
+      BrickInfo bi{0, -1, 1, b};
+      double cc[6] = {0, 0, 0, 0, 0, 0};
+      float4 tf = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (b < b_end) {
+        const int bz = b / (p.nbx * p.nby);
+        const int by = (b / p.nbx) % p.nby;
+        const int bx = b % p.nbx;
+        const int i0 = 2 * bx, j0 = 2 * by, k0 = 2 * bz;
+        const int i1 = min(i0 + 1, p.src.n[0] - 1);
+        const int j1 = min(j0 + 1, p.src.n[1] - 1);
+        const int k1 = min(k0 + 1, p.src.n[2] - 1);
+        cc[0] = canon(p.src.o[0], i0, p.src.h[0]);
+        cc[1] = canon(p.src.o[0], i1, p.src.h[0]);
+        cc[2] = canon(p.src.o[1], j0, p.src.h[1]);
+        cc[3] = canon(p.src.o[1], j1, p.src.h[1]);
+        cc[4] = canon(p.src.o[2], k0, p.src.h[2]);
+        cc[5] = canon(p.src.o[2], k1, p.src.h[2]);
+        const double blo[3] = {cc[0], cc[2], cc[4]};
+        const double bhi[3] = {cc[1], cc[3], cc[5]};
+        const double tlo[3] = {refx, refy, refz};
+        const double thi[3] = {thix, thiy, thiz};
+        double g2 = 0.0, f2 = 0.0;
+        bool near = true;
+        for (int a = 0; a < 3; ++a) {
+          double gap = __builtin_fmax(0.0, __builtin_fmax(blo[a] - thi[a], tlo[a] - bhi[a]));
+          double far = __builtin_fmax(bhi[a] - tlo[a], thi[a] - blo[a]);
+          g2 += gap * gap;
+          f2 += far * far;
+          near = near && (gap <= p.screen[a] + p.near_slack);
+        }
+        const double ulo = p.a_f - __builtin_sqrt(f2) * p.inv_cdt - p.margin;
+        const double uhi = p.a_f - __builtin_sqrt(g2) * p.inv_cdt + p.margin;
+        const int jlo = p.a_i + (int)__builtin_fmax(__builtin_floor(ulo), -1e9);
+        int jhi = p.a_i + (int)__builtin_fmax(__builtin_floor(uhi), -1e9);
+        jhi = min(jhi, p.nt - 1);
+        const bool dead = jhi < -1;
+        int vmask = 0;
+        for (int c = 0; c < 8; ++c) {
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          if (i0 + cx <= i1 && j0 + cy <= j1 && k0 + cz <= k1) vmask |= 1 << c;
+        }
+        bi.wlo = max(jlo, -2);
+        bi.whi = jhi;
+        bi.flags = (dead ? 1 : 0) | (near ? 2 : 0) | (vmask << 8);
+        tf = make_float4((float)(cc[0] - refx), (float)(cc[2] - refy), (float)(cc[4] - refz), 0.f);
+      }
+      tab_i[t] = make_int4(bi.wlo, bi.whi, bi.flags, bi.b);
+      tab_f[t] = tf;
+      for (int q = 0; q < 6; ++q) tab_c[t][q] = cc[q];
+    }
+    __syncthreads();
+
+    int n_chunks = 1;
+    if (MULTI) {
+      int wmax_round = 0;
+      for (int j = 0; j < G; ++j) {
+        const int4 ti = tab_i[j];
+        if (!(ti.z & 1)) wmax_round = max(wmax_round, ti.y - ti.x + 1);
+      }
+      n_chunks = (wmax_round + kWmax - 1) / kWmax;
+    }
+
+    for (int ch = 0; ch < n_chunks; ++ch) {
+      const int cs = ch * kWmax;
+      if (ch > 0) __syncthreads();
+      // ---- stage the slice windows of this round's bricks into LDS ----
+      for (int it = t; it < G * kWmax * kBrickCells; it += kThreads) {
+        const int c = it & 7;
+        const int kk = (it >> 3) % kWmax;
+        const int j = (it >> 3) / kWmax;
+        const int4 ti = tab_i[j];
+        if (ti.z & 1) continue;
+        const int k = ti.x + cs + kk;
+        if (k > ti.y) continue;
+        const int e = (j * kBrickCells + c) * kWmax + kk;
+        if constexpr (sizeof(T) == 4) {
+          const float4 hm = ring4(ring, p, k - 1, ti.w, c);
+          const float4 h0 = ring4(ring, p, k, ti.w, c);
+          const float4 h1 = ring4(ring, p, k + 1, ti.w, c);
+          float4 S, D, Tn;
+          S.x = h1.x - h0.x; S.y = h1.y - h0.y; S.z = h1.z - h0.z; S.w = h1.w - h0.w;
+          D.x = (h0.x - hm.x) * inv_dt; D.y = (h0.y - hm.y) * inv_dt;
+          D.z = (h0.z - hm.z) * inv_dt; D.w = (h0.w - hm.w) * inv_dt;
+          Tn.x = S.x * inv_dt - D.x; Tn.y = S.y * inv_dt - D.y;
+          Tn.z = S.z * inv_dt - D.z; Tn.w = S.w * inv_dt - D.w;
+          lds[e] = h0;
+          lds[PU + e] = S;
+          lds[2 * PU + e] = D;
+          lds[3 * PU + e] = Tn;
+        } else {
+          double hm[4], h0[4], h1[4], S[4], D[4], Tn[4];
+          ring4(ring, p, k - 1, ti.w, c, hm);
+          ring4(ring, p, k, ti.w, c, h0);
+          ring4(ring, p, k + 1, ti.w, c, h1);
+          for (int q = 0; q < 4; ++q) {
+            S[q] = h1[q] - h0[q];
+            D[q] = (h0[q] - hm[q]) * inv_dt;
+            Tn[q] = S[q] * inv_dt - D[q];
+          }
+          double2* l2 = (double2*)lds;
+          l2[e] = make_double2(h0[0], h0[1]);
+          l2[PU + e] = make_double2(h0[2], h0[3]);
+          l2[2 * PU + e] = make_double2(S[0], S[1]);
+          l2[3 * PU + e] = make_double2(S[2], S[3]);
+          l2[4 * PU + e] = make_double2(D[0], D[1]);
+          l2[5 * PU + e] = make_double2(D[2], D[3]);
+          l2[6 * PU + e] = make_double2(Tn[0], Tn[1]);
+          l2[7 * PU + e] = make_double2(Tn[2], Tn[3]);
+        }
+      }
+      __syncthreads();
+
+      // ---- pair loop over this round's source cells ----
+      float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
+      for (int j = 0; j < G; ++j) {
+        const int4 ti = tab_i[j];
+        if (ti.z & 1) continue;
+        const float4 tf = tab_f[j];
+        const bool near = (ti.z & 2) != 0;
+        const int vmask = ti.z >> 8;
+        const int lo_c = ti.x + cs;
+        const int hi_c = min(ti.y, lo_c + kWmax - 1);
+        const int base = j * kBrickCells * kWmax - lo_c;
+        const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
+        double bc[6];
+        if constexpr (sizeof(T) == 8) {
+          for (int q = 0; q < 6; ++q) bc[q] = tab_c[j][q];
+        }
+        int s_base = 0;
+        if (FP) {
+          const int b = ti.w;
+          const int bz = b / (p.nbx * p.nby);
+          const int by = (b / p.nbx) % p.nby;
+          const int bx = b % p.nbx;
+          s_base = 2 * bx + p.src.n[0] * (2 * by + p.src.n[1] * 2 * bz);
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          if (!((vmask >> c) & 1)) continue;
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          bool act = true;
+          if (near) {
+            const double ddx = rox - tab_c[j][cx];
+            const double ddy = roy - tab_c[j][2 + cy];
+            const double ddz = roz - tab_c[j][4 + cz];  // near bricks only
+            if (canon_screened(ddx, ddy, ddz, p.screen)) {
+              act = false;
+              if (FP && cs == 0) n_scr += 1;
+            }
+          }
+          if (!act) continue;
+          if constexpr (sizeof(T) == 4) {
+            const float dx = cx ? d0x - hsx : d0x;
+            const float dy = cy ? d0y - hsy : d0y;
+            const float dz = cz ? d0z - hsz : d0z;
+            float m, f, ri;
+            index_f32(dx, dy, dz, af32, icdt32, halfg,
+                      [&]() {
+                        return canon_u(rox - tab_c[j][cx], roy - tab_c[j][2 + cy],
+                                       roz - tab_c[j][4 + cz], p.a_f, p.inv_cdt);
+                      },
+                      m, f, ri);
+            const int k = p.a_i + (int)m;
+            const int kc = min(max(k, ti.x), MULTI ? ti.y : hi_c);
+            if (MULTI && (kc < lo_c || kc > hi_c)) continue;
+            if (FP) {
+              if (k >= -1) {
+                const int s = s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz);
+                n_live += 1;
+                sum_k += (unsigned long long)(long long)k;
+                sum_kw += (unsigned long long)(long long)k * (unsigned long long)(s + 1);
+              }
+              continue;
+            }
+            const int e = base + c * kWmax + kc;
+            const float4 hv = lds[e];
+            const float4 Sv = lds[PU + e];
+            const float4 Dv = lds[2 * PU + e];
+            const float4 Tv = lds[3 * PU + e];
+            const float ri2 = ri * ri;
+            const float ri3 = ri2 * ri;
+            const float rho = __builtin_fmaf(f, Sv.x, hv.x);
+            const float jx = __builtin_fmaf(f, Sv.y, hv.y);
+            const float jy = __builtin_fmaf(f, Sv.z, hv.z);
+            const float jz = __builtin_fmaf(f, Sv.w, hv.w);
+            const float rhod = __builtin_fmaf(f, Tv.x, Dv.x);
+            const float jdx = __builtin_fmaf(f, Tv.y, Dv.y);
+            const float jdy = __builtin_fmaf(f, Tv.z, Dv.z);
+            const float jdz = __builtin_fmaf(f, Tv.w, Dv.w);
+            const float a = __builtin_fmaf(rho, ri3, rhod * ri2);
+            bE[0] = __builtin_fmaf(dx, a, bE[0]);
+            bE[1] = __builtin_fmaf(dy, a, bE[1]);
+            bE[2] = __builtin_fmaf(dz, a, bE[2]);
+            bE[0] = __builtin_fmaf(-jdx, ri, bE[0]);
+            bE[1] = __builtin_fmaf(-jdy, ri, bE[1]);
+            bE[2] = __builtin_fmaf(-jdz, ri, bE[2]);
+            const float Kx = __builtin_fmaf(jx, ri3, jdx * ri2);
+            const float Ky = __builtin_fmaf(jy, ri3, jdy * ri2);
+            const float Kz = __builtin_fmaf(jz, ri3, jdz * ri2);
+            bB[0] = __builtin_fmaf(Ky, dz, bB[0]);
+            bB[0] = __builtin_fmaf(-Kz, dy, bB[0]);
+            bB[1] = __builtin_fmaf(Kz, dx, bB[1]);
+            bB[1] = __builtin_fmaf(-Kx, dz, bB[1]);
+            bB[2] = __builtin_fmaf(Kx, dy, bB[2]);
+            bB[2] = __builtin_fmaf(-Ky, dx, bB[2]);
+          } else {
+            const double dx = rox - bc[cx];
+            const double dy = roy - bc[2 + cy];
+            const double dz = roz - bc[4 + cz];
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            const double R = __builtin_sqrt(r2);
+            const double u = p.a_f - R * p.inv_cdt;
+            const double m = __builtin_fmax(__builtin_floor(u), -1e9);
+            const double f = u - m;
+            const int k = p.a_i + (int)m;
+            const int kc = min(max(k, ti.x), MULTI ? ti.y : hi_c);
+            if (MULTI && (kc < lo_c || kc > hi_c)) continue;
+            if (FP) {
+              if (k >= -1) {
+                const int s = s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz);
+                n_live += 1;
+                sum_k += (unsigned long long)(long long)k;
+                sum_kw += (unsigned long long)(long long)k * (unsigned long long)(s + 1);
+              }
+              continue;
+            }
+            // 1/R: hardware reciprocal refined by two Newton steps
+            double ri = __builtin_amdgcn_rcp(R);
+            double er = __builtin_fma(-R, ri, 1.0);
+            ri = __builtin_fma(ri, er, ri);
+            er = __builtin_fma(-R, ri, 1.0);
+            ri = __builtin_fma(ri, er, ri);
+            const double ri2 = ri * ri;
+            const double ri3 = ri2 * ri;
+            const double2* l2 = (const double2*)lds;
+            const int e = base + c * kWmax + kc;
+            const double2 h01 = l2[e], h23 = l2[PU + e];
+            const double2 S01 = l2[2 * PU + e], S23 = l2[3 * PU + e];
+            const double2 D01 = l2[4 * PU + e], D23 = l2[5 * PU + e];
+            const double2 T01 = l2[6 * PU + e], T23 = l2[7 * PU + e];
+            const double rho = __builtin_fma(f, S01.x, h01.x);
+            const double jx = __builtin_fma(f, S01.y, h01.y);
+            const double jy = __builtin_fma(f, S23.x, h23.x);
+            const double jz = __builtin_fma(f, S23.y, h23.y);
+            const double rhod = __builtin_fma(f, T01.x, D01.x);
+            const double jdx = __builtin_fma(f, T01.y, D01.y);
+            const double jdy = __builtin_fma(f, T23.x, D23.x);
+            const double jdz = __builtin_fma(f, T23.y, D23.y);
+            const double a = __builtin_fma(rho, ri3, rhod * ri2);
+            dE[0] = __builtin_fma(dx, a, dE[0]);
+            dE[1] = __builtin_fma(dy, a, dE[1]);
+            dE[2] = __builtin_fma(dz, a, dE[2]);
+            dE[0] = __builtin_fma(-jdx, ri, dE[0]);
+            dE[1] = __builtin_fma(-jdy, ri, dE[1]);
+            dE[2] = __builtin_fma(-jdz, ri, dE[2]);
+            const double Kx = __builtin_fma(jx, ri3, jdx * ri2);
+            const double Ky = __builtin_fma(jy, ri3, jdy * ri2);
+            const double Kz = __builtin_fma(jz, ri3, jdz * ri2);
+            dB[0] = __builtin_fma(Ky, dz, dB[0]);
+            dB[0] = __builtin_fma(-Kz, dy, dB[0]);
+            dB[1] = __builtin_fma(Kz, dx, dB[1]);
+            dB[1] = __builtin_fma(-Kx, dz, dB[1]);
+            dB[2] = __builtin_fma(Kx, dy, dB[2]);
+            dB[2] = __builtin_fma(-Ky, dx, dB[2]);
+          }
+        }
+      }
+      if constexpr (sizeof(T) == 4) {
+        if (!FP) {
+          for (int a = 0; a < 3; ++a) {
+            two_sum_acc(sE[a], cE[a], bE[a]);
+            two_sum_acc(sB[a], cB[a], bB[a]);
+          }
+        }
+      }
+    }
+  }
+
+  if (!valid) return;
+  const long long n_obs = (long long)p.obs.n[0] * p.obs.n[1] * p.obs.n[2];
+  const long long o = (long long)ix + (long long)p.obs.n[0] * ((long long)iy + (long long)p.obs.n[1] * iz);
+  if (FP) {
+    atomicAdd(&p.fp[o * 4 + 0], n_live);
+    atomicAdd(&p.fp[o * 4 + 1], sum_k);
+    atomicAdd(&p.fp[o * 4 + 2], sum_kw);
+    atomicAdd(&p.fp[o * 4 + 3], n_scr);
+    return;
+  }
+  double tot[6];
+  if constexpr (sizeof(T) == 4) {
+    for (int a = 0; a < 3; ++a) {
+      tot[a] = (double)sE[a] + (double)cE[a];
+      tot[3 + a] = (double)sB[a] + (double)cB[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      tot[a] = dE[a];
+      tot[3 + a] = dB[a];
+    }
+  }
+  if (p.direct) {
+    for (int a = 0; a < 3; ++a) {
+      const double e = tot[a] * p.pref, bb = tot[3 + a] * p.pref;
+      if (p.out_f64) {
+        ((double*)p.E)[a * n_obs + o] = e;
+        ((double*)p.B)[a * n_obs + o] = bb;
+      } else {
+        ((float*)p.E)[a * n_obs + o] = (float)e;
+        ((float*)p.B)[a * n_obs + o] = (float)bb;
+      }
+    }
+  } else {
+    for (int a = 0; a < 6; ++a) p.partial[((long long)split * 6 + a) * n_obs + o] = tot[a];
+  }
+}
+
+__global__ void epilogue_kernel(EpilogueParams p) {
+  const long long total = p.n_obs * 6;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long comp = i / p.n_obs;
+    const long long o = i - comp * p.n_obs;
+    double s = 0.0;
+    for (int q = 0; q < p.n_splits; ++q) s += p.partial[((long long)q * 6 + comp) * p.n_obs + o];
+    const double v = s * p.pref;
+    void* dst = comp < 3 ? p.E : p.B;
+    const long long at = (comp % 3) * p.n_obs + o;
+    if (p.out_f64)
+      ((double*)dst)[at] = v;
+    else
+      ((float*)dst)[at] = (float)v;
+  }
+}
+
+__global__ void zero_kernel(uint4* p, unsigned long long n16, unsigned char* tail, int ntail) {
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (unsigned long long)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+template <typename T>
+__global__ void ingest_kernel(const T* slice, T* slot, GridD src, int nbx, int nby) {
+  const long long n = (long long)src.n[0] * src.n[1] * src.n[2];
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(s % src.n[0]);
+    const int j = (int)((s / src.n[0]) % src.n[1]);
+    const int k = (int)(s / ((long long)src.n[0] * src.n[1]));
+    const long long b = (long long)(i >> 1) + (long long)nbx * ((j >> 1) + (long long)nby * (k >> 1));
+    const int c = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    T* dst = slot + (b * kBrickCells + c) * 4;
+    dst[0] = slice[s];
+    dst[1] = slice[n + s];
+    dst[2] = slice[2 * n + s];
+    dst[3] = slice[3 * n + s];
+  }
+}
+
+__global__ void fill_zero_fields(void* E, void* B, long long n, int f64) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (f64) {
+      ((double*)E)[i] = 0.0;
+      ((double*)B)[i] = 0.0;
+    } else {
+      ((float*)E)[i] = 0.f;
+      ((float*)B)[i] = 0.f;
+    }
+  }
+}
+
+// One thread per (observation point, source cell): the slice decision taken
+// by the pair kernels, from the same coordinate construction (tile reference
+// point, brick corner, cell offset) and the same index code.
+__global__ void dump_kernel(DumpParams p) {
+  const long long ns = (long long)p.src.n[0] * p.src.n[1] * p.src.n[2];
+  const long long no = (long long)p.obs.n[0] * p.obs.n[1] * p.obs.n[2];
+  const long long total = ns * no;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (long long)gridDim.x * blockDim.x) {
+    const long long o = q / ns;
+    const long long s = q - o * ns;
+    const int ix = (int)(o % p.obs.n[0]);
+    const int iy = (int)((o / p.obs.n[0]) % p.obs.n[1]);
+    const int iz = (int)(o / ((long long)p.obs.n[0] * p.obs.n[1]));
+    const int si = (int)(s % p.src.n[0]);
+    const int sj = (int)((s / p.src.n[0]) % p.src.n[1]);
+    const int sk = (int)(s / ((long long)p.src.n[0] * p.src.n[1]));
+    const double rox = canon(p.obs.o[0], ix, p.obs.h[0]);
+    const double roy = canon(p.obs.o[1], iy, p.obs.h[1]);
+    const double roz = canon(p.obs.o[2], iz, p.obs.h[2]);
+    const double rsx = canon(p.src.o[0], si, p.src.h[0]);
+    const double rsy = canon(p.src.o[1], sj, p.src.h[1]);
+    const double rsz = canon(p.src.o[2], sk, p.src.h[2]);
+    int code;
+    if (canon_screened(rox - rsx, roy - rsy, roz - rsz, p.screen)) {
+      code = INT32_MIN;
+    } else {
+      int k;
+      if (p.use_f64) {
+        const double u = canon_u(rox - rsx, roy - rsy, roz - rsz, p.a_f, p.inv_cdt);
+        k = p.a_i + (int)__builtin_fmax(__builtin_floor(u), -1e9);
+      } else {
+        const int tx0 = (ix / kTileEdge) * kTileEdge, ty0 = (iy / kTileEdge) * kTileEdge,
+                  tz0 = (iz / kTileEdge) * kTileEdge;
+        const double refx = canon(p.obs.o[0], tx0, p.obs.h[0]);
+        const double refy = canon(p.obs.o[1], ty0, p.obs.h[1]);
+        const double refz = canon(p.obs.o[2], tz0, p.obs.h[2]);
+        const float xo = (float)(rox - refx), yo = (float)(roy - refy), zo = (float)(roz - refz);
+        const double bxc = canon(p.src.o[0], si & ~1, p.src.h[0]);
+        const double byc = canon(p.src.o[1], sj & ~1, p.src.h[1]);
+        const double bzc = canon(p.src.o[2], sk & ~1, p.src.h[2]);
+        const float d0x = xo - (float)(bxc - refx);
+        const float d0y = yo - (float)(byc - refy);
+        const float d0z = zo - (float)(bzc - refz);
+        const float dx = (si & 1) ? d0x - (float)p.src.h[0] : d0x;
+        const float dy = (sj & 1) ? d0y - (float)p.src.h[1] : d0y;
+        const float dz = (sk & 1) ? d0z - (float)p.src.h[2] : d0z;
+        float m, f, ri;
+        index_f32(dx, dy, dz, (float)p.a_f, (float)p.inv_cdt, 0.5f - p.guard,
+                  [&]() { return canon_u(rox - rsx, roy - rsy, roz - rsz, p.a_f, p.inv_cdt); }, m, f,
+                  ri);
+        k = p.a_i + (int)m;
+      }
+      code = k < -1 ? -2 : k;
+    }
+    p.out[q] = code;
+  }
+}
+
+int grid_for(long long n, int block) {
+  long long g = (n + block - 1) / block;
+  if (g > 65536) g = 65536;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_zero(void* p, unsigned long long bytes, hipStream_t s) {
+  const unsigned long long n16 = bytes / 16;
+  const int ntail = (int)(bytes - n16 * 16);
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for((long long)(n16 > 0 ? n16 : 1), 256)), dim3(256), 0, s,
+                     (uint4*)p, n16, (unsigned char*)p + n16 * 16, ntail);
+  return hipGetLastError();
+}
+
+hipError_t launch_ingest(const void* slice, void* slot, const GridD& src, int nbx, int nby,
+                         int is_f64, hipStream_t s) {
+  const long long n = (long long)src.n[0] * src.n[1] * src.n[2];
+  if (n == 0) return hipSuccess;
+  if (is_f64)
+    hipLaunchKernelGGL(ingest_kernel<double>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       (const double*)slice, (double*)slot, src, nbx, nby);
+  else
+    hipLaunchKernelGGL(ingest_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       (const float*)slice, (float*)slot, src, nbx, nby);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk,
+                        hipStream_t s) {
+  dim3 grid(p.n_wg), block(kThreads);
+#define JEFI_LAUNCH(T, G, FPM, MUL) \
+  hipLaunchKernelGGL((pair_kernel<T, G, FPM, MUL>), grid, block, 0, s, p)
+  if (is_f64) {
+    if (fingerprint) {
+      if (multi_chunk) JEFI_LAUNCH(double, 2, true, true); else JEFI_LAUNCH(double, 2, true, false);
+    } else {
+      if (multi_chunk) JEFI_LAUNCH(double, 2, false, true); else JEFI_LAUNCH(double, 2, false, false);
+    }
+  } else {
+    if (fingerprint) {
+      if (multi_chunk) JEFI_LAUNCH(float, 4, true, true); else JEFI_LAUNCH(float, 4, true, false);
+    } else {
+      if (multi_chunk) JEFI_LAUNCH(float, 4, false, true); else JEFI_LAUNCH(float, 4, false, false);
+    }
+  }
+#undef JEFI_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s) {
+  if (p.n_obs == 0) return hipSuccess;
+  hipLaunchKernelGGL(epilogue_kernel, dim3(grid_for(p.n_obs * 6, 256)), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_fields(void* E, void* B, long long n_obs, int out_f64, hipStream_t s) {
+  if (n_obs == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_fields, dim3(grid_for(3 * n_obs, 256)), dim3(256), 0, s, E, B, n_obs,
+                     out_f64);
+  return hipGetLastError();
+}
+
+hipError_t launch_dump(const DumpParams& p, hipStream_t s) {
+  const long long ns = (long long)p.src.n[0] * p.src.n[1] * p.src.n[2];
+  const long long no = (long long)p.obs.n[0] * p.obs.n[1] * p.obs.n[2];
+  if (ns * no == 0) return hipSuccess;
+  hipLaunchKernelGGL(dump_kernel, dim3(grid_for(ns * no, 256)), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace jefi

@@ -1,0 +1,293 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: the slice index is bit-exact (per-pair dumps on small problems,
+per-point fingerprints taken by the field kernel itself on larger ones);
+E and B agree per component in relative L2 within 1e-12 (FP64 path) and
+1e-5 (FP32 compensated path)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.compare import rel_l2
+from workloads import Grid, Problem, blob_history, centred_grid, Blob
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+_ORACLE_CACHE = {}
+
+
+def _oracle(p, sel=None, kind="fields"):
+    """Oracle results cached per problem within the test session."""
+    key = (p.name, kind, None if sel is None else tuple(int(v) for v in sel))
+    if key not in _ORACLE_CACHE:
+        if kind == "fields":
+            _ORACLE_CACHE[key] = oracle.eval_problem(p, sel=sel)
+        else:
+            _ORACLE_CACHE[key] = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest,
+                                                          p.c, p.screen, sel=sel)
+    return _ORACLE_CACHE[key]
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests import _gpu as G
+    return G
+
+
+_PROBLEMS = {}
+
+
+def _medium():
+    if "medium" not in _PROBLEMS:
+        _PROBLEMS["medium"] = workloads.config_medium()
+    return _PROBLEMS["medium"]
+
+
+def _large():
+    if "large" not in _PROBLEMS:
+        _PROBLEMS["large"] = workloads.config_large()
+    return _PROBLEMS["large"]
+
+
+def _assert_fields(Eg, Bg, Er, Br, tol, label=""):
+    e, fe = rel_l2(Eg, Er)
+    b, fb = rel_l2(Bg, Br)
+    print(f"{label} rel L2 E={['%.2e' % x for x in e]} B={['%.2e' % x for x in b]}", flush=True)
+    assert np.all(np.isfinite(Eg)) and np.all(np.isfinite(Bg))
+    assert max(e + b) <= tol, (e, b)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tiny_fields(prec):
+    G = _gpu()
+    p = workloads.config_tiny()
+    Er, Br = oracle.eval_problem(p)
+    Eg, Bg = G.gpu_eval(p, prec)
+    _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"tiny {prec}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_tiny_slice_index_bit_exact(prec):
+    G = _gpu()
+    p = workloads.config_tiny()
+    ref = oracle.slice_index_dump(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+    got = G.gpu_dump(p, prec)
+    assert np.array_equal(got, ref)
+    fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+    fp = G.gpu_fingerprint(p, prec)
+    assert np.array_equal(fp, fp_ref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_medium_fields_and_fingerprint(prec):
+    G = _gpu()
+    p = _medium()
+    Er, Br = _oracle(p)
+    Eg, Bg = G.gpu_eval(p, prec)
+    _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"medium {prec}")
+    fp_ref = _oracle(p, kind="fp")
+    fp = G.gpu_fingerprint(p, prec)
+    assert np.array_equal(fp, fp_ref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_large_sampled(prec):
+    """64^3 x 64^3, 128 slices, at full size in the launch shape the bench
+    times; 192 seeded observation points checked against the oracle one by
+    one, fingerprints too."""
+    G = _gpu()
+    p = _large()
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(p.obs.size, size=192, replace=False))
+    Er, Br = _oracle(p, sel=sel)
+    Eg, Bg = G.gpu_eval(p, prec)
+    _assert_fields(Eg[:, sel], Bg[:, sel], Er, Br, TOL[prec], f"large {prec}")
+    fp_ref = _oracle(p, sel=sel, kind="fp")
+    fp = G.gpu_fingerprint(p, prec)
+    assert np.array_equal(fp[sel], fp_ref)
+
+
+def _ragged_problem(seed, smooth=True):
+    rng = np.random.default_rng(seed)
+    ns = tuple(int(v) for v in rng.integers(3, 19, 3))
+    no = tuple(int(v) for v in rng.integers(1, 21, 3))
+    hs = float(rng.uniform(0.04, 0.09))
+    src = Grid(ns, tuple(rng.uniform(-0.5, -0.2, 3)), (hs, hs * rng.uniform(0.8, 1.2), hs))
+    obs = Grid(no, tuple(rng.uniform(-0.6, 0.2, 3)), tuple(rng.uniform(0.03, 0.1, 3)))
+    dt = float(rng.uniform(0.3, 0.7)) * hs
+    nt = int(rng.integers(4, 40))
+    s_old = int(rng.integers(0, 50))
+    newest = s_old + nt - 1
+    c = float(rng.uniform(0.8, 1.25))
+    if smooth:
+        blobs = workloads.draw_blobs(rng, 3, (-0.5, 0.3))
+        hist = blob_history(src, blobs, list(range(s_old, newest + 1)), dt)
+    else:
+        hist = rng.normal(size=(nt, 4, src.size))
+    t = newest * dt - float(rng.uniform(0, 1.5)) * dt
+    screen = tuple(float(v) for v in rng.uniform(0.0, 0.06, 3))
+    return Problem(f"ragged{seed}", src, obs, hist, dt, t, 0.0, newest, c, screen)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_ragged_random_problems(seed):
+    """Ragged grid sizes (partial tiles and bricks), unequal spacings, c != 1,
+    t between slices, a window not starting at step 0, arbitrary screening."""
+    G = _gpu()
+    p = _ragged_problem(seed)
+    Er, Br = oracle.eval_problem(p)
+    for prec in ["f64", "f32"]:
+        Eg, Bg = G.gpu_eval(p, prec)
+        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"{p.name} {prec}")
+        fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+        assert np.array_equal(G.gpu_fingerprint(p, prec), fp_ref)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_rough_histories_fp64(seed):
+    """White-noise histories (no smoothness to hide interpolation mistakes)."""
+    G = _gpu()
+    p = _ragged_problem(100 + seed, smooth=False)
+    Er, Br = oracle.eval_problem(p)
+    Eg, Bg = G.gpu_eval(p, "f64")
+    _assert_fields(Eg, Bg, Er, Br, TOL["f64"], f"{p.name} rough")
+
+
+def test_long_windows_take_the_chunked_path():
+    """dt much smaller than the spacing: slice windows longer than one LDS
+    staging chunk."""
+    G = _gpu()
+    src = centred_grid((6, 5, 7), 0.1)
+    obs = src.shifted_cells(3, 1, -2)
+    dt = 0.01
+    nt = 120
+    blobs = [Blob(1.0, 0.15, (0.0, 0.05, 0.0), (0.3, 0.0, 0.2)), Blob(-0.5, 0.1, (0.1, 0, 0), (0, 0.4, 0))]
+    hist = blob_history(src, blobs, nt, dt)
+    p = Problem("chunked", src, obs, hist, dt, (nt - 1) * dt, 0.0, nt - 1, 1.0, workloads.default_screen(src))
+    Er, Br = oracle.eval_problem(p)
+    for prec in ["f64", "f32"]:
+        Eg, Bg = G.gpu_eval(p, prec)
+        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"chunked {prec}")
+        fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+        assert np.array_equal(G.gpu_fingerprint(p, prec), fp_ref)
+
+
+def test_exact_integer_boundaries_dump():
+    """R/(c dt) exactly integral (d = 0.5, dt = 0.25): both device index
+    paths return the canonical k, including on the slice boundary."""
+    G = _gpu()
+    src = Grid((3, 3, 3), (0.0, 0.0, 0.0), (0.5, 0.5, 0.5))
+    obs = Grid((5, 4, 3), (0.5, 0.0, 0.0), (0.5, 0.5, 0.5))
+    nt, dt = 12, 0.25
+    p = Problem("int", src, obs, np.zeros((nt, 4, src.size)), dt, (nt - 1) * dt, 0.0, nt - 1, 1.0,
+                (0.0, 0.0, 0.0))
+    ref = oracle.slice_index_dump(src, obs, nt, dt, p.t, 0.0, nt - 1, 1.0, (0.0, 0.0, 0.0))
+    for prec in ["f64", "f32"]:
+        assert np.array_equal(G.gpu_dump(p, prec), ref)
+
+
+def test_random_pairs_dump_bit_exact():
+    """Many random pairs with large R/(c dt): the FP32 guard band holds."""
+    G = _gpu()
+    rng = np.random.default_rng(5)
+    for trial in range(4):
+        src = Grid((17, 13, 11), tuple(rng.uniform(-1, 0, 3)), tuple(rng.uniform(0.01, 0.05, 3)))
+        obs = Grid((19, 7, 9), tuple(rng.uniform(0, 2, 3)), tuple(rng.uniform(0.01, 0.1, 3)))
+        dt = float(rng.uniform(0.002, 0.02))
+        nt = 1000
+        newest = nt - 1 + int(rng.integers(0, 10 ** 6))
+        t = newest * dt - float(rng.uniform(0, 3)) * dt
+        p = Problem("rp", src, obs, np.zeros((0, 4, 0)), dt, t, 0.0, newest, 1.0, (0.0, 0.0, 0.0))
+        ref = oracle.slice_index_dump(src, obs, nt, dt, t, 0.0, newest, 1.0, (0.0, 0.0, 0.0))
+        for prec in ["f64", "f32"]:
+            assert np.array_equal(G.gpu_dump(p, prec), ref)
+
+
+def test_edge_cases():
+    import torch
+    import paper_2104_05426_amd as J
+    G = _gpu()
+    base = workloads.config_tiny()
+    # empty observation grid: no-op
+    empty = Grid((0, 0, 0), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    E, B = G.gpu_eval(base, "f32", obs=empty)
+    assert E.shape == (3, 0)
+    # a single source cell, nt = 1 (the only slice, zero before it)
+    src1 = Grid((1, 1, 1), (0.0, 0.0, 0.0), (0.1, 0.1, 0.1))
+    obs1 = Grid((3, 2, 2), (0.03, 0.02, 0.01), (0.05, 0.05, 0.05))
+    h = np.zeros((1, 4, 1))
+    h[0, :, 0] = [1.0, 0.5, -0.25, 2.0]
+    p1 = Problem("one", src1, obs1, h, 0.1, 0.0, 0.0, 0, 1.0, (0.0, 0.0, 0.0))
+    Er, Br = oracle.eval_problem(p1)
+    for prec in ["f64", "f32"]:
+        Eg, Bg = G.gpu_eval(p1, prec)
+        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"one-cell {prec}")
+    # evaluation time long before the window: every stencil is in the past -> zeros
+    pe = Problem("past", base.src, base.obs, base.hist, base.dt, -5.0, 0.0, base.newest, 1.0, base.screen)
+    Eg, Bg = G.gpu_eval(pe, "f32")
+    assert np.all(Eg == 0.0) and np.all(Bg == 0.0)
+    # FP64 output dtype from the FP32 path, and FP32 output from the FP64 path
+    Er, Br = oracle.eval_problem(base)
+    Eg, Bg = G.gpu_eval(base, "f32", out_dtype="f64")
+    _assert_fields(Eg, Bg, Er, Br, TOL["f32"], "f32->f64 out")
+    Eg, Bg = G.gpu_eval(base, "f64", out_dtype="f32")
+    _assert_fields(Eg, Bg, Er, Br, 1e-6, "f64->f32 out")
+
+
+def test_invalid_arguments_leave_outputs_untouched():
+    import torch
+    import paper_2104_05426_amd as J
+    _gpu()
+    p = workloads.config_tiny()
+    store, h = J.upload_history(p.src, p.hist, J.JEFI_F32, newest=p.newest)
+    E = torch.full((3, p.obs.size), 7.0, device="cuda")
+    B = torch.full((3, p.obs.size), 7.0, device="cuda")
+    with pytest.raises(J.JefiError):
+        J.jefi_eval_fields(p.src, h, p.dt, p.nt, p.obs, p.t + 1.0, E, B)
+    with pytest.raises(J.JefiError):
+        J.jefi_eval_fields(p.src, h, p.dt, p.nt, p.obs, p.t, E, B,
+                           J.jefi_options_default(precision=J.JEFI_PREC_F64))
+    torch.cuda.synchronize()
+    assert bool((E == 7.0).all()) and bool((B == 7.0).all())
+
+
+def test_ring_wraparound_matches_fresh_upload():
+    """Pushing past the capacity overwrites the oldest slots; evaluating the
+    last nt steps of a wrapped ring equals a ring holding just those steps."""
+    import torch
+    import paper_2104_05426_amd as J
+    G = _gpu()
+    src = centred_grid((9, 7, 6), 0.05)
+    obs = src.shifted_cells(4, -2, 1)
+    dt = 0.025
+    total, cap, nt = 75, 32, 30
+    blobs = [Blob(0.7, 0.08, (0.02, 0.0, -0.03), (0.4, 0.2, 0.0))]
+    hall = blob_history(src, blobs, total, dt)
+    store, h = J.upload_history(src, hall, J.JEFI_F32, capacity=cap)
+    assert h.newest == total - 1
+    E = torch.empty((3, obs.size), device="cuda")
+    B = torch.empty((3, obs.size), device="cuda")
+    t = (total - 1) * dt
+    J.jefi_eval_fields(src, h, dt, nt, obs, t, E, B)
+    torch.cuda.synchronize()
+    p = Problem("wrap", src, obs, hall[total - nt:], dt, t, 0.0, total - 1, 1.0, workloads.default_screen(src))
+    Er, Br = oracle.eval_problem(p)
+    _assert_fields(E.double().cpu().numpy(), B.double().cpu().numpy(), Er, Br, TOL["f32"], "wrap")
+    Eg2, Bg2 = G.gpu_eval(p, "f32")
+    assert np.array_equal(Eg2, E.double().cpu().numpy()) and np.array_equal(Bg2, B.double().cpu().numpy())
+
+
+def test_deterministic_repeat():
+    G = _gpu()
+    p = _medium()
+    for prec in ["f64", "f32"]:
+        a = G.gpu_eval(p, prec)
+        b = G.gpu_eval(p, prec)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -88,23 +88,30 @@ def blob_history(g: Grid, blobs: Sequence[Blob], steps: Sequence[int] | int,
 
     rho_i(r, t) = q_i (2 pi sigma_i^2)^(-3/2) exp(-|r - c_i - v_i t|^2 / (2 sigma_i^2)).
     Returns FP64 ``h[len(steps)][4][n_cells]`` for absolute ``steps`` at
-    times ``t0 + s * dt`` (an int means steps 0..n-1).
+    times ``t0 + s * dt`` (an int means steps 0..n-1).  The Gaussian factors
+    per axis, so each slice is a sum of outer products of 1-D profiles.
     """
     if isinstance(steps, (int, np.integer)):
         steps = list(range(int(steps)))
-    r = cell_centres(g)
+    nx, ny, nz = g.n
+    ax = [g.origin[a] + np.arange(g.n[a], dtype=np.float64) * g.spacing[a] for a in range(3)]
+    q = np.array([b.q for b in blobs], dtype=np.float64)
+    sig = np.array([b.sigma for b in blobs], dtype=np.float64)
+    cen = np.array([b.centre for b in blobs], dtype=np.float64).reshape(-1, 3)
+    vel = np.array([b.velocity for b in blobs], dtype=np.float64).reshape(-1, 3)
+    norm = q * (2.0 * math.pi * sig ** 2) ** -1.5
     out = np.zeros((len(steps), 4, g.size), dtype=np.float64)
+    if len(blobs) == 0:
+        return out
+    weights = np.stack([norm, norm * vel[:, 0], norm * vel[:, 1], norm * vel[:, 2]])  # [4][K]
     for si, s in enumerate(steps):
         t = t0 + s * dt
-        for b in blobs:
-            c = np.asarray(b.centre) + np.asarray(b.velocity) * t
-            d2 = ((r - c) ** 2).sum(axis=1)
-            norm = b.q * (2.0 * math.pi * b.sigma ** 2) ** -1.5
-            rho = norm * np.exp(-d2 / (2.0 * b.sigma ** 2))
-            out[si, 0] += rho
-            out[si, 1] += rho * b.velocity[0]
-            out[si, 2] += rho * b.velocity[1]
-            out[si, 3] += rho * b.velocity[2]
+        c = cen + vel * t
+        prof = [np.exp(-((ax[a][None, :] - c[:, a:a + 1]) ** 2) / (2.0 * sig[:, None] ** 2))
+                for a in range(3)]  # [K][n_a]
+        zy = (prof[2][:, :, None] * prof[1][:, None, :]).reshape(len(blobs), nz * ny)  # [K][nz*ny]
+        for ch in range(4):
+            out[si, ch] = ((zy * weights[ch][:, None]).T @ prof[0]).reshape(-1)
     return out
 
 
@@ -174,6 +181,7 @@ class Problem:
     newest: int = 0             # absolute step of hist[-1]
     c: float = 1.0
     screen: Tuple[float, float, float] = field(default=(0.0, 0.0, 0.0))
+    blobs: list = field(default_factory=list)   # sources, when generated from blobs
 
     @property
     def nt(self) -> int:
@@ -186,8 +194,10 @@ class Problem:
 
 def _problem(name, src, obs, blobs, nt, dt):
     hist = blob_history(src, blobs, nt, dt)
-    return Problem(name, src, obs, hist, dt, t=(nt - 1) * dt, t0=0.0,
-                   newest=nt - 1, c=1.0, screen=default_screen(src))
+    p = Problem(name, src, obs, hist, dt, t=(nt - 1) * dt, t0=0.0,
+                newest=nt - 1, c=1.0, screen=default_screen(src))
+    p.blobs = list(blobs)
+    return p
 
 
 def config_tiny() -> Problem:
@@ -245,7 +255,7 @@ def batch_instances(count: int = 64, seed: int = 3, with_history: bool = True) -
             p = Problem(f"batch{i}-{es}^3x{eo}^3-nt{nt}", src, obs,
                         np.zeros((0, 4, 0)), dt, t=(nt - 1) * dt, newest=nt - 1,
                         screen=default_screen(src))
-        p.blobs = blobs  # type: ignore[attr-defined]
+        p.blobs = list(blobs)
         out.append(p)
     return out
 
