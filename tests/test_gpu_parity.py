@@ -204,7 +204,7 @@ def test_random_pairs_dump_bit_exact():
         nt = 1000
         newest = nt - 1 + int(rng.integers(0, 10 ** 6))
         t = newest * dt - float(rng.uniform(0, 3)) * dt
-        p = Problem("rp", src, obs, np.zeros((0, 4, 0)), dt, t, 0.0, newest, 1.0, (0.0, 0.0, 0.0))
+        p = Problem("rp", src, obs, np.zeros((nt, 4, 0)), dt, t, 0.0, newest, 1.0, (0.0, 0.0, 0.0))
         ref = oracle.slice_index_dump(src, obs, nt, dt, t, 0.0, newest, 1.0, (0.0, 0.0, 0.0))
         for prec in ["f64", "f32"]:
             assert np.array_equal(G.gpu_dump(p, prec), ref)
