@@ -60,11 +60,17 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 
 // FP32 slice decision with the FP64 fallback near slice boundaries.
 // Returns floor(u) (clamped below at -1e9) and the weight f.
+// FP32 squared separation, x^2 + (y^2 + z^2) without contraction; the fast
+// pair path forms the same expression from per-brick partial squares.
+__device__ __forceinline__ float r2_f32(float dx, float dy, float dz) {
+  return dx * dx + (dy * dy + dz * dz);
+}
+
 template <class Canon>
 __device__ __forceinline__ void index_f32(float dx, float dy, float dz, float af, float icdt,
                                           float halfg, Canon canon_fn, float& m, float& f,
                                           float& ri) {
-  float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+  float r2 = r2_f32(dx, dy, dz);
   ri = __builtin_amdgcn_rsqf(r2);
   float R = r2 * ri;
   float u = __builtin_fmaf(-R, icdt, af);
@@ -121,10 +127,86 @@ __device__ __forceinline__ void ring4(const double* ring, const PairParams& p, i
   out[0] = lo.x; out[1] = lo.y; out[2] = hi.x; out[3] = hi.y;
 }
 
-// Brick table entry computed by one thread per brick and round.
-struct BrickInfo {
-  int wlo, whi, flags, b;  // flags: bit0 dead, bit1 near, bits 8..15 valid-cell mask
+// Geometry of one observation tile: first/last point indices, the FP64
+// reference point (first point) and the far corner of its box.
+struct TileGeom {
+  int ix0, iy0, iz0, ix1, iy1, iz1;
+  double refx, refy, refz, thix, thiy, thiz;
 };
+
+__device__ __forceinline__ TileGeom tile_geom(const PairParams& p, int tile) {
+  TileGeom g;
+  const int tx = tile % p.ntx;
+  const int ty = (tile / p.ntx) % p.nty;
+  const int tz = tile / (p.ntx * p.nty);
+  g.ix0 = tx * kTileEdge;
+  g.iy0 = ty * kTileEdge;
+  g.iz0 = tz * kTileEdge;
+  g.ix1 = min(g.ix0 + kTileEdge - 1, p.obs.n[0] - 1);
+  g.iy1 = min(g.iy0 + kTileEdge - 1, p.obs.n[1] - 1);
+  g.iz1 = min(g.iz0 + kTileEdge - 1, p.obs.n[2] - 1);
+  g.refx = canon(p.obs.o[0], g.ix0, p.obs.h[0]);
+  g.refy = canon(p.obs.o[1], g.iy0, p.obs.h[1]);
+  g.refz = canon(p.obs.o[2], g.iz0, p.obs.h[2]);
+  g.thix = canon(p.obs.o[0], g.ix1, p.obs.h[0]);
+  g.thiy = canon(p.obs.o[1], g.iy1, p.obs.h[1]);
+  g.thiz = canon(p.obs.o[2], g.iz1, p.obs.h[2]);
+  return g;
+}
+
+// Window of slices brick b can need for the tile: FP64 min/max separations
+// of the two boxes of cell centres bound every pair's slice index (FP
+// subtraction, squaring, sums and sqrt are monotone, so the bounds hold for
+// the rounded canonical values too).  ti = (wlo, whi, flags, b) with flags
+// bit0 = dead (whole window before the oldest slice), bit1 = near (some pair
+// may be screened), bits 8..15 = valid cells; tf = brick corner relative to
+// the tile reference in FP32; cc = canonical x0, x1, y0, y1, z0, z1.
+__device__ __forceinline__ void brick_info(const PairParams& p, const TileGeom& g, int b, int b_end,
+                                           int4& ti, float4& tf, double cc[6]) {
+  ti = make_int4(0, -1, 1, b);
+  tf = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int q = 0; q < 6; ++q) cc[q] = 0.0;
+  if (b >= b_end) return;
+  const int bz = b / (p.nbx * p.nby);
+  const int by = (b / p.nbx) % p.nby;
+  const int bx = b % p.nbx;
+  const int i0 = 2 * bx, j0 = 2 * by, k0 = 2 * bz;
+  const int i1 = min(i0 + 1, p.src.n[0] - 1);
+  const int j1 = min(j0 + 1, p.src.n[1] - 1);
+  const int k1 = min(k0 + 1, p.src.n[2] - 1);
+  cc[0] = canon(p.src.o[0], i0, p.src.h[0]);
+  cc[1] = canon(p.src.o[0], i1, p.src.h[0]);
+  cc[2] = canon(p.src.o[1], j0, p.src.h[1]);
+  cc[3] = canon(p.src.o[1], j1, p.src.h[1]);
+  cc[4] = canon(p.src.o[2], k0, p.src.h[2]);
+  cc[5] = canon(p.src.o[2], k1, p.src.h[2]);
+  const double blo[3] = {cc[0], cc[2], cc[4]};
+  const double bhi[3] = {cc[1], cc[3], cc[5]};
+  const double tlo[3] = {g.refx, g.refy, g.refz};
+  const double thi[3] = {g.thix, g.thiy, g.thiz};
+  double g2 = 0.0, f2 = 0.0;
+  bool near = true;
+  for (int a = 0; a < 3; ++a) {
+    const double gap = __builtin_fmax(0.0, __builtin_fmax(blo[a] - thi[a], tlo[a] - bhi[a]));
+    const double far = __builtin_fmax(bhi[a] - tlo[a], thi[a] - blo[a]);
+    g2 += gap * gap;
+    f2 += far * far;
+    near = near && (gap <= p.screen[a] + p.near_slack);
+  }
+  const double ulo = p.a_f - __builtin_sqrt(f2) * p.inv_cdt - p.margin;
+  const double uhi = p.a_f - __builtin_sqrt(g2) * p.inv_cdt + p.margin;
+  const int jlo = p.a_i + (int)__builtin_fmax(__builtin_floor(ulo), -1e9);
+  int jhi = p.a_i + (int)__builtin_fmax(__builtin_floor(uhi), -1e9);
+  jhi = min(jhi, p.nt - 1);
+  const bool dead = jhi < -1;
+  int vmask = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+    if (i0 + cx <= i1 && j0 + cy <= j1 && k0 + cz <= k1) vmask |= 1 << c;
+  }
+  ti = make_int4(max(jlo, -2), jhi, (dead ? 1 : 0) | (near ? 2 : 0) | (vmask << 8), b);
+  tf = make_float4((float)(cc[0] - g.refx), (float)(cc[2] - g.refy), (float)(cc[4] - g.refz), 0.f);
+}
 
 template <typename T, int G, bool FP, bool MULTI>
 __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
@@ -139,13 +221,9 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
   const int bid = xcd_remap((int)blockIdx.x, p.n_wg);
   const int split = bid / p.n_tiles;
   const int tile = bid - split * p.n_tiles;
-  const int tx = tile % p.ntx;
-  const int ty = (tile / p.ntx) % p.nty;
-  const int tz = tile / (p.ntx * p.nty);
-  const int ix0 = tx * kTileEdge, iy0 = ty * kTileEdge, iz0 = tz * kTileEdge;
-  const int ix1 = min(ix0 + kTileEdge - 1, p.obs.n[0] - 1);
-  const int iy1 = min(iy0 + kTileEdge - 1, p.obs.n[1] - 1);
-  const int iz1 = min(iz0 + kTileEdge - 1, p.obs.n[2] - 1);
+  const TileGeom tg = tile_geom(p, tile);
+  const int ix0 = tg.ix0, iy0 = tg.iy0, iz0 = tg.iz0;
+  const int ix1 = tg.ix1, iy1 = tg.iy1, iz1 = tg.iz1;
   const int t = (int)threadIdx.x;
   const int w = t >> 6, l = t & 63;
   const int ix = ix0 + (w & 1) * 4 + (l & 3);
@@ -154,12 +232,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
   const bool valid = ix <= ix1 && iy <= iy1 && iz <= iz1;
   const int cix = min(ix, ix1), ciy = min(iy, iy1), ciz = min(iz, iz1);
 
-  const double refx = canon(p.obs.o[0], ix0, p.obs.h[0]);
-  const double refy = canon(p.obs.o[1], iy0, p.obs.h[1]);
-  const double refz = canon(p.obs.o[2], iz0, p.obs.h[2]);
-  const double thix = canon(p.obs.o[0], ix1, p.obs.h[0]);
-  const double thiy = canon(p.obs.o[1], iy1, p.obs.h[1]);
-  const double thiz = canon(p.obs.o[2], iz1, p.obs.h[2]);
+  const double refx = tg.refx, refy = tg.refy, refz = tg.refz;
   const double rox = canon(p.obs.o[0], cix, p.obs.h[0]);
   const double roy = canon(p.obs.o[1], ciy, p.obs.h[1]);
   const double roz = canon(p.obs.o[2], ciz, p.obs.h[2]);
@@ -182,54 +255,11 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
   for (int rb = b_begin; rb < b_end; rb += G) {
     __syncthreads();  // the previous round's readers are done with LDS and the table
     if (t < G) {
-      const int b = rb + t;
-      BrickInfo bi{0, -1, 1, b};
-      double cc[6] = {0, 0, 0, 0, 0, 0};
-      float4 tf = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (b < b_end) {
-        const int bz = b / (p.nbx * p.nby);
-        const int by = (b / p.nbx) % p.nby;
-        const int bx = b % p.nbx;
-        const int i0 = 2 * bx, j0 = 2 * by, k0 = 2 * bz;
-        const int i1 = min(i0 + 1, p.src.n[0] - 1);
-        const int j1 = min(j0 + 1, p.src.n[1] - 1);
-        const int k1 = min(k0 + 1, p.src.n[2] - 1);
-        cc[0] = canon(p.src.o[0], i0, p.src.h[0]);
-        cc[1] = canon(p.src.o[0], i1, p.src.h[0]);
-        cc[2] = canon(p.src.o[1], j0, p.src.h[1]);
-        cc[3] = canon(p.src.o[1], j1, p.src.h[1]);
-        cc[4] = canon(p.src.o[2], k0, p.src.h[2]);
-        cc[5] = canon(p.src.o[2], k1, p.src.h[2]);
-        const double blo[3] = {cc[0], cc[2], cc[4]};
-        const double bhi[3] = {cc[1], cc[3], cc[5]};
-        const double tlo[3] = {refx, refy, refz};
-        const double thi[3] = {thix, thiy, thiz};
-        double g2 = 0.0, f2 = 0.0;
-        bool near = true;
-        for (int a = 0; a < 3; ++a) {
-          double gap = __builtin_fmax(0.0, __builtin_fmax(blo[a] - thi[a], tlo[a] - bhi[a]));
-          double far = __builtin_fmax(bhi[a] - tlo[a], thi[a] - blo[a]);
-          g2 += gap * gap;
-          f2 += far * far;
-          near = near && (gap <= p.screen[a] + p.near_slack);
-        }
-        const double ulo = p.a_f - __builtin_sqrt(f2) * p.inv_cdt - p.margin;
-        const double uhi = p.a_f - __builtin_sqrt(g2) * p.inv_cdt + p.margin;
-        const int jlo = p.a_i + (int)__builtin_fmax(__builtin_floor(ulo), -1e9);
-        int jhi = p.a_i + (int)__builtin_fmax(__builtin_floor(uhi), -1e9);
-        jhi = min(jhi, p.nt - 1);
-        const bool dead = jhi < -1;
-        int vmask = 0;
-        for (int c = 0; c < 8; ++c) {
-          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-          if (i0 + cx <= i1 && j0 + cy <= j1 && k0 + cz <= k1) vmask |= 1 << c;
-        }
-        bi.wlo = max(jlo, -2);
-        bi.whi = jhi;
-        bi.flags = (dead ? 1 : 0) | (near ? 2 : 0) | (vmask << 8);
-        tf = make_float4((float)(cc[0] - refx), (float)(cc[2] - refy), (float)(cc[4] - refz), 0.f);
-      }
-      tab_i[t] = make_int4(bi.wlo, bi.whi, bi.flags, bi.b);
+      int4 ti;
+      float4 tf;
+      double cc[6];
+      brick_info(p, tg, rb + t, b_end, ti, tf, cc);
+      tab_i[t] = ti;
       tab_f[t] = tf;
       for (int q = 0; q < 6; ++q) tab_c[t][q] = cc[q];
     }
@@ -499,6 +529,437 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Fast pair kernel: every slice window of the launch fits one LDS staging
+// chunk.  Per round of G bricks: the raw slices of the next round are loaded
+// into registers while the current round is computed; LDS holds (h, S, D, T)
+// planes of [cell][slot] entries with one pad entry per cell.  Full bricks
+// outside the screening range take a two-phase path: slice decisions for all
+// 8 cells first (one divergent FP64 fix-up if any falls in the guard band),
+// then branch-free LDS reads and field arithmetic.
+constexpr int kCellStride = kWmax + 1;
+
+struct D4 {
+  double x, y, z, w;
+};
+
+__device__ __forceinline__ void load_raw(const float* ring, const PairParams& p, int jj, int b, int c,
+                                         float4& out) {
+  out = ring4(ring, p, jj, b, c);
+}
+
+__device__ __forceinline__ void load_raw(const double* ring, const PairParams& p, int jj, int b, int c,
+                                         D4& out) {
+  double v[4];
+  ring4(ring, p, jj, b, c, v);
+  out = D4{v[0], v[1], v[2], v[3]};
+}
+
+__device__ __forceinline__ void zero_raw(float4& v) { v = make_float4(0.f, 0.f, 0.f, 0.f); }
+__device__ __forceinline__ void zero_raw(D4& v) { v = D4{0.0, 0.0, 0.0, 0.0}; }
+
+template <typename T>
+struct RawOf;
+template <>
+struct RawOf<float> {
+  using type = float4;
+};
+template <>
+struct RawOf<double> {
+  using type = D4;
+};
+
+// Entry (h, S, D, T) of slot k from raw slices k-1, k, k+1, written to the planes.
+__device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const float4& hm, const float4& h0,
+                                          const float4& h1, float inv_dt) {
+  float4 S, D, Tn;
+  S.x = h1.x - h0.x; S.y = h1.y - h0.y; S.z = h1.z - h0.z; S.w = h1.w - h0.w;
+  D.x = (h0.x - hm.x) * inv_dt; D.y = (h0.y - hm.y) * inv_dt;
+  D.z = (h0.z - hm.z) * inv_dt; D.w = (h0.w - hm.w) * inv_dt;
+  Tn.x = S.x * inv_dt - D.x; Tn.y = S.y * inv_dt - D.y;
+  Tn.z = S.z * inv_dt - D.z; Tn.w = S.w * inv_dt - D.w;
+  lds[idx] = h0;
+  lds[PU + idx] = S;
+  lds[2 * PU + idx] = D;
+  lds[3 * PU + idx] = Tn;
+}
+
+__device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const D4& hm, const D4& h0,
+                                          const D4& h1, double inv_dt) {
+  const double a[4] = {hm.x, hm.y, hm.z, hm.w};
+  const double b[4] = {h0.x, h0.y, h0.z, h0.w};
+  const double c[4] = {h1.x, h1.y, h1.z, h1.w};
+  double S[4], D[4], Tn[4];
+  for (int q = 0; q < 4; ++q) {
+    S[q] = c[q] - b[q];
+    D[q] = (b[q] - a[q]) * inv_dt;
+    Tn[q] = S[q] * inv_dt - D[q];
+  }
+  double2* l2 = (double2*)lds;
+  l2[idx] = make_double2(b[0], b[1]);
+  l2[PU + idx] = make_double2(b[2], b[3]);
+  l2[2 * PU + idx] = make_double2(S[0], S[1]);
+  l2[3 * PU + idx] = make_double2(S[2], S[3]);
+  l2[4 * PU + idx] = make_double2(D[0], D[1]);
+  l2[5 * PU + idx] = make_double2(D[2], D[3]);
+  l2[6 * PU + idx] = make_double2(Tn[0], Tn[1]);
+  l2[7 * PU + idx] = make_double2(Tn[2], Tn[3]);
+}
+
+// Field contribution of one pair from its LDS entry (FP32).
+__device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, float f, float ri, float dx,
+                                            float dy, float dz, float bE[3], float bB[3]) {
+  const float4 hv = lds[e];
+  const float4 Sv = lds[PU + e];
+  const float4 Dv = lds[2 * PU + e];
+  const float4 Tv = lds[3 * PU + e];
+  const float rho = __builtin_fmaf(f, Sv.x, hv.x);
+  const float jx = __builtin_fmaf(f, Sv.y, hv.y);
+  const float jy = __builtin_fmaf(f, Sv.z, hv.z);
+  const float jz = __builtin_fmaf(f, Sv.w, hv.w);
+  const float rhod = __builtin_fmaf(f, Tv.x, Dv.x);
+  const float jdx = __builtin_fmaf(f, Tv.y, Dv.y);
+  const float jdy = __builtin_fmaf(f, Tv.z, Dv.z);
+  const float jdz = __builtin_fmaf(f, Tv.w, Dv.w);
+  // E += d/R^2 (rho/R + rho_dot) - J_dot/R ;  B += (J/R + J_dot) x d/R^2
+  const float ri2 = ri * ri;
+  const float ux = dx * ri2, uy = dy * ri2, uz = dz * ri2;
+  const float ap = __builtin_fmaf(rho, ri, rhod);
+  bE[0] = __builtin_fmaf(ux, ap, bE[0]);
+  bE[1] = __builtin_fmaf(uy, ap, bE[1]);
+  bE[2] = __builtin_fmaf(uz, ap, bE[2]);
+  bE[0] = __builtin_fmaf(-jdx, ri, bE[0]);
+  bE[1] = __builtin_fmaf(-jdy, ri, bE[1]);
+  bE[2] = __builtin_fmaf(-jdz, ri, bE[2]);
+  const float Lx = __builtin_fmaf(jx, ri, jdx);
+  const float Ly = __builtin_fmaf(jy, ri, jdy);
+  const float Lz = __builtin_fmaf(jz, ri, jdz);
+  bB[0] = __builtin_fmaf(Ly, uz, bB[0]);
+  bB[0] = __builtin_fmaf(-Lz, uy, bB[0]);
+  bB[1] = __builtin_fmaf(Lz, ux, bB[1]);
+  bB[1] = __builtin_fmaf(-Lx, uz, bB[1]);
+  bB[2] = __builtin_fmaf(Lx, uy, bB[2]);
+  bB[2] = __builtin_fmaf(-Ly, ux, bB[2]);
+}
+
+// Field contribution of one pair from its LDS entry (FP64).
+__device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, double f, double R, double dx,
+                                            double dy, double dz, double dE[3], double dB[3]) {
+  double ri = __builtin_amdgcn_rcp(R);
+  double er = __builtin_fma(-R, ri, 1.0);
+  ri = __builtin_fma(ri, er, ri);
+  er = __builtin_fma(-R, ri, 1.0);
+  ri = __builtin_fma(ri, er, ri);
+  const double2* l2 = (const double2*)lds;
+  const double2 h01 = l2[e], h23 = l2[PU + e];
+  const double2 S01 = l2[2 * PU + e], S23 = l2[3 * PU + e];
+  const double2 D01 = l2[4 * PU + e], D23 = l2[5 * PU + e];
+  const double2 T01 = l2[6 * PU + e], T23 = l2[7 * PU + e];
+  const double rho = __builtin_fma(f, S01.x, h01.x);
+  const double jx = __builtin_fma(f, S01.y, h01.y);
+  const double jy = __builtin_fma(f, S23.x, h23.x);
+  const double jz = __builtin_fma(f, S23.y, h23.y);
+  const double rhod = __builtin_fma(f, T01.x, D01.x);
+  const double jdx = __builtin_fma(f, T01.y, D01.y);
+  const double jdy = __builtin_fma(f, T23.x, D23.x);
+  const double jdz = __builtin_fma(f, T23.y, D23.y);
+  const double ri2 = ri * ri;
+  const double ux = dx * ri2, uy = dy * ri2, uz = dz * ri2;
+  const double ap = __builtin_fma(rho, ri, rhod);
+  dE[0] = __builtin_fma(ux, ap, dE[0]);
+  dE[1] = __builtin_fma(uy, ap, dE[1]);
+  dE[2] = __builtin_fma(uz, ap, dE[2]);
+  dE[0] = __builtin_fma(-jdx, ri, dE[0]);
+  dE[1] = __builtin_fma(-jdy, ri, dE[1]);
+  dE[2] = __builtin_fma(-jdz, ri, dE[2]);
+  const double Lx = __builtin_fma(jx, ri, jdx);
+  const double Ly = __builtin_fma(jy, ri, jdy);
+  const double Lz = __builtin_fma(jz, ri, jdz);
+  dB[0] = __builtin_fma(Ly, uz, dB[0]);
+  dB[0] = __builtin_fma(-Lz, uy, dB[0]);
+  dB[1] = __builtin_fma(Lz, ux, dB[1]);
+  dB[1] = __builtin_fma(-Lx, uz, dB[1]);
+  dB[2] = __builtin_fma(Lx, uy, dB[2]);
+  dB[2] = __builtin_fma(-Ly, ux, dB[2]);
+}
+
+struct FpAcc {
+  unsigned long long n_live = 0, sum_k = 0, sum_kw = 0, n_scr = 0;
+  __device__ __forceinline__ void add(int k, int s) {
+    if (k >= -1) {
+      n_live += 1;
+      sum_k += (unsigned long long)(long long)k;
+      sum_kw += (unsigned long long)(long long)k * (unsigned long long)(s + 1);
+    }
+  }
+};
+
+template <typename T, int G, bool FP>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
+  using Raw = typename RawOf<T>::type;
+  constexpr int NPL = Traits<T>::kPlanes;
+  constexpr int CELLS = G * kBrickCells;
+  constexpr int PU = CELLS * kCellStride;
+  constexpr int EPT = G * kBrickCells * kWmax / kThreads;  // staged entries per thread
+  constexpr int NRAW = EPT + 2;
+  constexpr int NQ = kWmax / EPT;
+  static_assert(EPT >= 1 && EPT * kThreads == G * kBrickCells * kWmax, "staging map");
+  __shared__ float4 lds[NPL * PU];
+  __shared__ int4 tab_i[2][G];
+  __shared__ float4 tab_f[2][G];
+  __shared__ double tab_c[2][G][6];
+
+  const int bid = xcd_remap((int)blockIdx.x, p.n_wg);
+  const int split = bid / p.n_tiles;
+  const int tile = bid - split * p.n_tiles;
+  const TileGeom tg = tile_geom(p, tile);
+  const int t = (int)threadIdx.x;
+  const int w = t >> 6, l = t & 63;
+  const int ix = tg.ix0 + (w & 1) * 4 + (l & 3);
+  const int iy = tg.iy0 + ((w >> 1) & 1) * 4 + ((l >> 2) & 3);
+  const int iz = tg.iz0 + (w >> 2) * 4 + (l >> 4);
+  const bool valid = ix <= tg.ix1 && iy <= tg.iy1 && iz <= tg.iz1;
+  const int cix = min(ix, tg.ix1), ciy = min(iy, tg.iy1), ciz = min(iz, tg.iz1);
+  const double rox = canon(p.obs.o[0], cix, p.obs.h[0]);
+  const double roy = canon(p.obs.o[1], ciy, p.obs.h[1]);
+  const double roz = canon(p.obs.o[2], ciz, p.obs.h[2]);
+  const float xo = (float)(rox - tg.refx), yo = (float)(roy - tg.refy), zo = (float)(roz - tg.refz);
+  const float hsx = (float)p.src.h[0], hsy = (float)p.src.h[1], hsz = (float)p.src.h[2];
+  const float af32 = (float)p.a_f, icdt32 = (float)p.inv_cdt, halfg = 0.5f - p.guard;
+  const T inv_dt = (T)p.inv_dt;
+  const T* ring = (const T*)p.ring;
+  const int b_begin = split * p.bricks_per_split;
+  const int b_end = min(b_begin + p.bricks_per_split, p.n_bricks);
+
+  // staging assignment: cell fastest (coalesced 16-byte loads along a brick)
+  const int sc = t & 7;
+  const int sq = (t >> 3) % NQ;
+  const int sj = (t >> 3) / NQ;
+
+  float sE[3] = {0.f, 0.f, 0.f}, cE[3] = {0.f, 0.f, 0.f};
+  float sB[3] = {0.f, 0.f, 0.f}, cB[3] = {0.f, 0.f, 0.f};
+  double dE[3] = {0.0, 0.0, 0.0}, dB[3] = {0.0, 0.0, 0.0};
+  FpAcc fpa;
+  Raw raw[NRAW];
+
+  auto make_table = [&](int rb, int buf) {
+    if (t < G) {
+      int4 ti;
+      float4 tf;
+      double cc[6];
+      brick_info(p, tg, rb + t, b_end, ti, tf, cc);
+      tab_i[buf][t] = ti;
+      tab_f[buf][t] = tf;
+      for (int q = 0; q < 6; ++q) tab_c[buf][t][q] = cc[q];
+    }
+  };
+  auto load_round = [&](int buf) {
+    const int4 ti = tab_i[buf][sj];
+    const int k0 = ti.x + sq * EPT;
+#pragma unroll
+    for (int r = 0; r < NRAW; ++r) {
+      if (ti.z & 1)
+        zero_raw(raw[r]);
+      else
+        load_raw(ring, p, k0 - 1 + r, ti.w, sc, raw[r]);
+    }
+  };
+  auto write_round = [&](int buf) {
+    const int4 ti = tab_i[buf][sj];
+    if (ti.z & 1) return;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      put_entry(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1],
+                raw[e + 2], inv_dt);
+  };
+
+  int buf = 0;
+  if (b_begin < b_end) {
+    make_table(b_begin, 0);
+    __syncthreads();
+    load_round(0);
+  }
+  for (int rb = b_begin; rb < b_end; rb += G) {
+    write_round(buf);
+    make_table(rb + G, buf ^ 1);
+    __syncthreads();
+    if (rb + G < b_end) load_round(buf ^ 1);
+
+    float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
+    for (int j = 0; j < G; ++j) {
+      const int4 ti = tab_i[buf][j];
+      if (ti.z & 1) continue;
+      const int lo = ti.x;
+      const int hiw = min(ti.y - lo, kWmax - 1);
+      const int off = p.a_i - lo;  // window slot of slice index m: m + off
+      const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
+      const int mlo = -off, mhi = hiw - off;
+      const double* bc = tab_c[buf][j];
+      int s_base = 0;
+      if (FP) {
+        const int b = ti.w;
+        const int bz = b / (p.nbx * p.nby);
+        const int by = (b / p.nbx) % p.nby;
+        const int bx = b % p.nbx;
+        s_base = 2 * bx + p.src.n[0] * (2 * by + p.src.n[1] * 2 * bz);
+      }
+      const bool fast = (ti.z & 0xff02) == 0xff00;  // all 8 cells present, no screening possible
+      if constexpr (sizeof(T) == 4) {
+        const float4 tf = tab_f[buf][j];
+        const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
+        const float d1x = d0x - hsx, d1y = d0y - hsy, d1z = d0z - hsz;
+        if (fast) {
+          const float x2[2] = {d0x * d0x, d1x * d1x};
+          const float y2[2] = {d0y * d0y, d1y * d1y};
+          const float z2[2] = {d0z * d0z, d1z * d1z};
+          const float yz[4] = {y2[0] + z2[0], y2[1] + z2[0], y2[0] + z2[1], y2[1] + z2[1]};
+          float ri[8], fr[8];
+          int m[8];
+          bool risky = false;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const float r2 = x2[c & 1] + yz[c >> 1];
+            ri[c] = __builtin_amdgcn_rsqf(r2);
+            const float R = r2 * ri[c];
+            const float u = __builtin_fmaf(-R, icdt32, af32);
+            const float fl = __builtin_floorf(u);
+            fr[c] = u - fl;
+            m[c] = (int)fl;
+            risky = risky || (__builtin_fabsf(fr[c] - 0.5f) > halfg);
+          }
+          if (risky) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+              if (__builtin_fabsf(fr[c] - 0.5f) > halfg) {
+                const double u64 = canon_u(rox - bc[c & 1], roy - bc[2 + ((c >> 1) & 1)],
+                                           roz - bc[4 + (c >> 2)], p.a_f, p.inv_cdt);
+                const double m64 = __builtin_floor(u64);
+                m[c] = (int)__builtin_fmax(m64, -1e9);
+                fr[c] = (float)(u64 - m64);
+              }
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            if (FP) {
+              const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+              fpa.add(p.a_i + m[c], s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz));
+              continue;
+            }
+            const int e = cellbase + c * kCellStride + min(max(m[c], mlo), mhi);
+            pair_fields(lds, PU, e, fr[c], ri[c], (c & 1) ? d1x : d0x, ((c >> 1) & 1) ? d1y : d0y,
+                        (c >> 2) ? d1z : d0z, bE, bB);
+          }
+        } else {
+          const int vmask = ti.z >> 8;
+          const bool near = (ti.z & 2) != 0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            if (!((vmask >> c) & 1)) continue;
+            const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+            if (near && canon_screened(rox - bc[cx], roy - bc[2 + cy], roz - bc[4 + cz], p.screen)) {
+              if (FP) fpa.n_scr += 1;
+              continue;
+            }
+            const float dx = cx ? d1x : d0x, dy = cy ? d1y : d0y, dz = cz ? d1z : d0z;
+            float mf, f, ri;
+            index_f32(dx, dy, dz, af32, icdt32, halfg,
+                      [&]() { return canon_u(rox - bc[cx], roy - bc[2 + cy], roz - bc[4 + cz], p.a_f, p.inv_cdt); },
+                      mf, f, ri);
+            const int mm = (int)mf;
+            if (FP) {
+              fpa.add(p.a_i + mm, s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz));
+              continue;
+            }
+            const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
+            pair_fields(lds, PU, e, f, ri, dx, dy, dz, bE, bB);
+          }
+        }
+      } else {
+        const double dx[2] = {rox - bc[0], rox - bc[1]};
+        const double dy[2] = {roy - bc[2], roy - bc[3]};
+        const double dz[2] = {roz - bc[4], roz - bc[5]};
+        const double x2[2] = {dx[0] * dx[0], dx[1] * dx[1]};
+        const double y2[2] = {dy[0] * dy[0], dy[1] * dy[1]};
+        const double z2[2] = {dz[0] * dz[0], dz[1] * dz[1]};
+        const int vmask = ti.z >> 8;
+        const bool near = (ti.z & 2) != 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          if (!fast) {
+            if (!((vmask >> c) & 1)) continue;
+            if (near && canon_screened(dx[cx], dy[cy], dz[cz], p.screen)) {
+              if (FP) fpa.n_scr += 1;
+              continue;
+            }
+          }
+          // (dx*dx + dy*dy) + dz*dz, as the canonical sequence
+          const double r2 = (x2[cx] + y2[cy]) + z2[cz];
+          const double R = __builtin_sqrt(r2);
+          const double u = p.a_f - R * p.inv_cdt;
+          const double fl = __builtin_floor(u);
+          const int mm = (int)__builtin_fmax(fl, -1e9);
+          if (FP) {
+            fpa.add(p.a_i + mm, s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz));
+            continue;
+          }
+          const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
+          pair_fields(lds, PU, e, u - fl, R, dx[cx], dy[cy], dz[cz], dE, dB);
+        }
+      }
+    }
+    if constexpr (sizeof(T) == 4) {
+      if (!FP) {
+        for (int a = 0; a < 3; ++a) {
+          two_sum_acc(sE[a], cE[a], bE[a]);
+          two_sum_acc(sB[a], cB[a], bB[a]);
+        }
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  if (!valid) return;
+  const long long n_obs = (long long)p.obs.n[0] * p.obs.n[1] * p.obs.n[2];
+  const long long o = (long long)ix + (long long)p.obs.n[0] * ((long long)iy + (long long)p.obs.n[1] * iz);
+  if (FP) {
+    atomicAdd(&p.fp[o * 4 + 0], fpa.n_live);
+    atomicAdd(&p.fp[o * 4 + 1], fpa.sum_k);
+    atomicAdd(&p.fp[o * 4 + 2], fpa.sum_kw);
+    atomicAdd(&p.fp[o * 4 + 3], fpa.n_scr);
+    return;
+  }
+  double tot[6];
+  if constexpr (sizeof(T) == 4) {
+    for (int a = 0; a < 3; ++a) {
+      tot[a] = (double)sE[a] + (double)cE[a];
+      tot[3 + a] = (double)sB[a] + (double)cB[a];
+    }
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      tot[a] = dE[a];
+      tot[3 + a] = dB[a];
+    }
+  }
+  if (p.direct) {
+    for (int a = 0; a < 3; ++a) {
+      const double e = tot[a] * p.pref, bb = tot[3 + a] * p.pref;
+      if (p.out_f64) {
+        ((double*)p.E)[a * n_obs + o] = e;
+        ((double*)p.B)[a * n_obs + o] = bb;
+      } else {
+        ((float*)p.E)[a * n_obs + o] = (float)e;
+        ((float*)p.B)[a * n_obs + o] = (float)bb;
+      }
+    }
+  } else {
+    for (int a = 0; a < 6; ++a) p.partial[((long long)split * 6 + a) * n_obs + o] = tot[a];
+  }
+}
+
 __global__ void epilogue_kernel(EpilogueParams p) {
   const long long total = p.n_obs * 6;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -649,6 +1110,15 @@ hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int mu
   dim3 grid(p.n_wg), block(kThreads);
 #define JEFI_LAUNCH(T, G, FPM, MUL) \
   hipLaunchKernelGGL((pair_kernel<T, G, FPM, MUL>), grid, block, 0, s, p)
+#define JEFI_FAST(T, G, FPM) hipLaunchKernelGGL((pair_kernel_fast<T, G, FPM>), grid, block, 0, s, p)
+  if (!multi_chunk) {
+    if (is_f64) {
+      if (fingerprint) JEFI_FAST(double, 2, true); else JEFI_FAST(double, 2, false);
+    } else {
+      if (fingerprint) JEFI_FAST(float, 4, true); else JEFI_FAST(float, 4, false);
+    }
+    return hipGetLastError();
+  }
   if (is_f64) {
     if (fingerprint) {
       if (multi_chunk) JEFI_LAUNCH(double, 2, true, true); else JEFI_LAUNCH(double, 2, true, false);
@@ -663,6 +1133,7 @@ hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int mu
     }
   }
 #undef JEFI_LAUNCH
+#undef JEFI_FAST
   return hipGetLastError();
 }
 
