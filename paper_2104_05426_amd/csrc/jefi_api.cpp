@@ -203,7 +203,7 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   p.n_tiles = p.ntx * p.nty * p.ntz;
   // Enough workgroups to fill 256 CUs several times over; splits of the
   // source bricks make up what the observation tiles alone do not give.
-  const long long target_wg = 2048;
+  const long long target_wg = 8192;
   if (p.n_tiles == 0 || p.n_bricks == 0) {
     plan->multi = 0;
     return JEFI_OK;  // nothing to launch
@@ -231,7 +231,7 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   double slo[3], shi[3], olo[3], ohi[3];
   grid_box(src, slo, shi);
   grid_box(obs, olo, ohi);
-  double rmax2 = 0.0, dt2 = 0.0, db2 = 0.0, hs = 0.0;
+  double rmax2 = 0.0, dt2 = 0.0, db2 = 0.0;
   for (int a = 0; a < 3; ++a) {
     const double far = std::fmax(std::fabs(shi[a] - olo[a]), std::fabs(ohi[a] - slo[a]));
     rmax2 += far * far;
@@ -239,18 +239,26 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
     const double be = (double)std::min(src->n[a] - 1, 1) * src->spacing[a];
     dt2 += te * te;
     db2 += be * be;
-    hs = std::fmax(hs, src->spacing[a]);
   }
   const double rmax = std::sqrt(rmax2), diam_t = std::sqrt(dt2), diam_b = std::sqrt(db2);
-  // FP32 index guard: bound |u32 - u64| for the FP32 sequence of the pair
-  // kernel (coordinates relative to the tile's first point, brick corner,
-  // cell offset; r2 by two FMAs; v_rsq_f32; R = r2*ri; u by one FMA) and
-  // double it.
+  // FP32 index guard: a bound on |u32 - u64| for the FP32 sequence of the
+  // pair kernels, with u = 2^-24 the FP32 unit roundoff:
+  //  - coordinates relative to the tile's first point, brick corner, cell
+  //    offset (three roundings deep): |d32 - d| <= u (3R + 2 D_tile + 3 h);
+  //  - r2 = x^2 + (y^2 + z^2): 3u relative, i.e. 1.5u on R; v_rsq_f32 taken
+  //    as 2 ulp (4u); R = r2 * ri one more rounding: 6.5u relative on R;
+  //  - u = fma(-R, 1/(c dt), a_f) with both constants rounded to FP32: u on
+  //    1/(c dt), u on a_f, u on the result.
+  // The band used is 1.25x that bound; a fractional part inside it sends
+  // the pair through the canonical FP64 sequence.
   const double eps = std::ldexp(1.0, -24);
-  const double e_coord = std::sqrt(3.0) * eps * (4.0 * rmax + 4.0 * diam_t + 4.0 * hs);
-  const double e_R = e_coord + 10.0 * eps * rmax;
-  const double e_u = ts.inv_cdt * e_R + eps * (ts.inv_cdt * rmax + 2.0);
-  double g = 2.0 * e_u + 1e-6;
+  double hsd2 = 0.0;
+  for (int a = 0; a < 3; ++a) hsd2 += src->spacing[a] * src->spacing[a];
+  const double e_coord = eps * (3.0 * rmax + 2.0 * diam_t + 3.0 * std::sqrt(hsd2));
+  const double e_R = e_coord + 7.5 * eps * rmax;
+  const double umax = ts.inv_cdt * rmax + 2.0;
+  const double e_u = ts.inv_cdt * e_R + eps * (umax + 1.0);
+  double g = 1.25 * e_u + 1e-7;
   if (!(g < 0.5)) g = 0.5;  // every pair then takes the FP64 path
   p.guard = (float)g;
   // Longest slice window any brick can need.
