@@ -259,7 +259,25 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   const double umax = ts.inv_cdt * rmax + 2.0;
   const double e_u = ts.inv_cdt * e_R + eps * (umax + 1.0);
   double g = 1.25 * e_u + 1e-7;
-  if (!(g < 0.5)) g = 0.5;  // every pair then takes the FP64 path
+  p.use_thr = 0;
+  if (!(g < 0.5)) {
+    g = 0.5;  // every pair then takes the FP64 path
+  } else {
+    // Guard-band pairs have floor(u64) in {N-1, N}, N the integer nearest
+    // u32; u is monotone in r2, so floor(u64) >= N iff r2 <= T(N), with T(N)
+    // the largest FP64 r2 whose canonical u reaches N.  Kernels build the
+    // table for every N the launch can meet.
+    const double ulow = std::floor(ts.a_f - rmax * ts.inv_cdt) - 2.0;
+    if (ulow > -1e9) {
+      const long long lo = (long long)ulow;
+      const long long n = 1 - lo + 1;
+      if (n <= kThrMax) {
+        p.use_thr = 1;
+        p.thr_lo = (int)lo;
+        p.thr_n = (int)n;
+      }
+    }
+  }
   p.guard = (float)g;
   // Longest slice window any brick can need.
   const double wb = std::floor((diam_t + diam_b) * ts.inv_cdt * (1.0 + 1e-12) + 2.0 * p.margin + 1e-6) + 3.0;

@@ -14,6 +14,8 @@ constexpr int kTileEdge = 8;
 constexpr int kThreads = 512;
 // Slice-window slots staged per source cell and launch variant.
 constexpr int kWmax = 32;
+// Largest table of slice-boundary thresholds a launch stages in LDS.
+constexpr int kThrMax = 512;
 
 struct GridD {
   int n[3];
@@ -43,6 +45,9 @@ struct PairParams {
   double margin;         // slack on box-derived slice bounds, slice units
   double near_slack;     // slack on the box screening test, length units
   float guard;           // FP32 index guard half-width, slice units
+  int use_thr;           // 1: decide guard-band pairs by the r2 threshold table
+  int thr_lo;            // table covers floor positions thr_lo .. thr_lo + thr_n - 1
+  int thr_n;
   const void* ring;      // device ring, library layout
   long long slot_elems;  // elements (of the ring dtype) per slot
   double* partial;       // FP64 [n_splits][6][n_obs] (unscaled sums)

@@ -50,6 +50,25 @@ __device__ __forceinline__ bool canon_screened(double dx, double dy, double dz, 
   return __builtin_sqrt(r2) == 0.0;
 }
 
+// Largest FP64 r2 >= 0 whose canonical retarded position a_f - sqrt(r2)/(c dt)
+// is >= N (-1 when even r2 = 0 falls short): a bisection over the ordered
+// bit patterns of the non-negative doubles, with the same correctly rounded
+// sqrt, multiply and subtract as the canonical sequence.
+__device__ __forceinline__ double r2_threshold(int N, double af, double icdt) {
+  const double n = (double)N;
+  if (!(af - __builtin_sqrt(0.0) * icdt >= n)) return -1.0;
+  unsigned long long lo = 0ull, hi = 0x7ff0000000000000ull;
+  while (hi - lo > 1ull) {
+    const unsigned long long mid = lo + ((hi - lo) >> 1);
+    const double x = __longlong_as_double((long long)mid);
+    if (af - __builtin_sqrt(x) * icdt >= n)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return __longlong_as_double((long long)lo);
+}
+
 // Map the hardware workgroup id so that consecutive logical ids land on the
 // same XCD (workgroups are dealt round-robin over the 8 XCDs).
 __device__ __forceinline__ int xcd_remap(int bid, int n) {
@@ -709,12 +728,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ int4 tab_i[2][G];
   __shared__ float4 tab_f[2][G];
   __shared__ double tab_c[2][G][6];
+  __shared__ double thr[sizeof(T) == 4 ? kThrMax : 1];
 
   const int bid = xcd_remap((int)blockIdx.x, p.n_wg);
   const int split = bid / p.n_tiles;
   const int tile = bid - split * p.n_tiles;
   const TileGeom tg = tile_geom(p, tile);
   const int t = (int)threadIdx.x;
+  if constexpr (sizeof(T) == 4) {
+    if (p.use_thr)
+      for (int i = t; i < p.thr_n; i += kThreads) thr[i] = r2_threshold(p.thr_lo + i, p.a_f, p.inv_cdt);
+  }
   const int w = t >> 6, l = t & 63;
   const int ix = tg.ix0 + (w & 1) * 4 + (l & 3);
   const int iy = tg.iy0 + ((w >> 1) & 1) * 4 + ((l >> 2) & 3);
@@ -829,14 +853,35 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             risky = risky || (__builtin_fabsf(fr[c] - 0.5f) > halfg);
           }
           if (risky) {
+            if (p.use_thr) {
+              // canonical r2 = (dx*dx + dy*dy) + dz*dz, parts shared by the 8 cells
+              const double ex[2] = {rox - bc[0], rox - bc[1]};
+              const double ey[2] = {roy - bc[2], roy - bc[3]};
+              const double ez[2] = {roz - bc[4], roz - bc[5]};
+              const double ez2[2] = {ez[0] * ez[0], ez[1] * ez[1]};
+              const double exy[4] = {ex[0] * ex[0] + ey[0] * ey[0], ex[1] * ex[1] + ey[0] * ey[0],
+                                     ex[0] * ex[0] + ey[1] * ey[1], ex[1] * ex[1] + ey[1] * ey[1]};
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-              if (__builtin_fabsf(fr[c] - 0.5f) > halfg) {
-                const double u64 = canon_u(rox - bc[c & 1], roy - bc[2 + ((c >> 1) & 1)],
-                                           roz - bc[4 + (c >> 2)], p.a_f, p.inv_cdt);
-                const double m64 = __builtin_floor(u64);
-                m[c] = (int)__builtin_fmax(m64, -1e9);
-                fr[c] = (float)(u64 - m64);
+              for (int c = 0; c < 8; ++c) {
+                if (__builtin_fabsf(fr[c] - 0.5f) > halfg) {
+                  const double r2 = exy[c & 3] + ez2[c >> 2];
+                  const int N = m[c] + (fr[c] > 0.5f ? 1 : 0);
+                  const int ti_ = min(max(N - p.thr_lo, 0), p.thr_n - 1);
+                  const int mn = r2 <= thr[ti_] ? N : N - 1;
+                  fr[c] += (float)(m[c] - mn);
+                  m[c] = mn;
+                }
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < 8; ++c) {
+                if (__builtin_fabsf(fr[c] - 0.5f) > halfg) {
+                  const double u64 = canon_u(rox - bc[c & 1], roy - bc[2 + ((c >> 1) & 1)],
+                                             roz - bc[4 + (c >> 2)], p.a_f, p.inv_cdt);
+                  const double m64 = __builtin_floor(u64);
+                  m[c] = (int)__builtin_fmax(m64, -1e9);
+                  fr[c] = (float)(u64 - m64);
+                }
               }
             }
           }
@@ -847,7 +892,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
               fpa.add(p.a_i + m[c], s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz));
               continue;
             }
-            const int e = cellbase + c * kCellStride + min(max(m[c], mlo), mhi);
+            // m <= mhi holds by the window bounds; below mlo lies the zero
+            // entry of pairs wholly before the oldest slice
+            const int e = cellbase + c * kCellStride + max(m[c], mlo);
             pair_fields(lds, PU, e, fr[c], ri[c], (c & 1) ? d1x : d0x, ((c >> 1) & 1) ? d1y : d0y,
                         (c >> 2) ? d1z : d0z, bE, bB);
           }
