@@ -27,6 +27,34 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 flop/clk
 METRIC = "G source-obs pairs/s (FP32-comp vs FP64, same GPU) at 1e-5 rel L2; p99 latency"
 
 
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ["jefi_kernels.hip", "jefi_internal.h", "jefi_api.cpp"]:
+        with open(os.path.join(ROOT, "paper_2104_05426_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(workload):
+    """HBM bytes per FP32 launch from the committed rocprofv3 counters, or
+    None when the kernel sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"pair_kernel_fast_f32_{workload}-64x64x64.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "`", "#")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch_f32"])
+    except (KeyError, ValueError):
+        return None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -173,7 +201,8 @@ def main():
                             "p99": round(float(np.percentile(r32["step_ms"], 99)), 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                     "traffic": None,
+                     "traffic": profiled_traffic(args.workload),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "kernel": "pair_kernel<float> (+ epilogue) per jefi_eval_fields, HIP events",
                      "flops_per_live_pair": FLOPS_PER_LIVE_PAIR},
     }
