@@ -103,7 +103,9 @@ typedef struct {
   int32_t screen_set;    /* 0: half the source spacing per axis (default) */
   int32_t precision;     /* jefi_precision (default JEFI_PREC_F32_COMP) */
   uint32_t flags;        /* reserved, 0 */
-  int32_t tile_config;   /* 0 = automatic; >0 selects a tuned launch shape */
+  int32_t tile_config;   /* launch shape: 0 = automatic (autotuned table, else a size
+                            heuristic), 1 = 8x8x8 observation tiles (512 threads),
+                            2 = 8x8x4 tiles (256 threads) */
 } jefi_options;
 
 const char* jefi_version(void);
@@ -141,6 +143,41 @@ jefi_status jefi_history_push(jefi_history* h, const jefi_grid* src, const void*
 jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt,
                              const jefi_grid* obs, double t, const jefi_fields* out,
                              const jefi_options* opt, void* stream);
+
+/* ---- batched evaluation (row: batched persistent launch) -------------------
+ * Many independent problems of uneven sizes in one persistent launch:
+ * workgroups pull (problem, observation tile, source split) items, heaviest
+ * first, from a device queue; the launch sequence (queue reset, threshold
+ * tables, persistent pair kernel, split reduction) is a hipGraph built once
+ * per stream workspace and replayed.  Each problem means what
+ * jefi_eval_fields means for the same arguments (results agree within the
+ * precision's tolerance; FP64 split sums may associate differently). */
+typedef struct {
+  jefi_grid src;
+  jefi_history hist;     /* each problem's own resident history */
+  double dt;
+  int32_t nt;
+  jefi_grid obs;
+  double t;
+  jefi_fields out;       /* each problem's own DEVICE outputs (must not overlap) */
+} jefi_problem;
+
+/* All problems share `opt` (precision, c, screening rule, launch shape);
+ * 0 <= n <= 65536.  Stream-ordered like jefi_eval_fields.  Validation of
+ * every problem precedes any device work: on EINVAL nothing is launched.
+ * The library keeps a per-(device, stream) workspace (descriptor tables,
+ * split partials, two pinned staging buffers and the graph): a call may wait
+ * for the upload of the call before last on the same stream. */
+jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream);
+
+/* Autotuner: times each launch shape on `probs` (one problem = single
+ * launch, several = batch), `reps` runs each after a warm-up, records the
+ * fastest for this size class (precision, log2 observation points per
+ * problem, log2 total pairs) so tile_config = 0 uses it, and persists the
+ * table to the file named by $JEFI_TUNE_CACHE when set.  Writes the outputs
+ * of the problems.  best_config / best_ms may be NULL. */
+jefi_status jefi_autotune(const jefi_problem* probs, int32_t n, const jefi_options* opt, int32_t reps,
+                          void* stream, int32_t* best_config, double* best_ms);
 
 /* ---- slice-decision diagnostics ------------------------------------------
  * The integer decisions the field kernels take, exposed for bit-exact

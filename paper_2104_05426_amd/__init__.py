@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE"
 EXPORTS = [
     "jefi_version", "jefi_last_error", "jefi_options_default", "jefi_history_bytes",
     "jefi_history_init", "jefi_history_push", "jefi_eval_fields", "jefi_slice_index_dump",
-    "jefi_slice_fingerprint",
+    "jefi_slice_fingerprint", "jefi_eval_batch", "jefi_autotune",
 ]
 
 
@@ -56,6 +56,11 @@ class jefi_options(C.Structure):
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("tile_config", C.c_int32)]
 
 
+class jefi_problem(C.Structure):
+    _fields_ = [("src", jefi_grid), ("hist", jefi_history), ("dt", C.c_double), ("nt", C.c_int32),
+                ("obs", jefi_grid), ("t", C.c_double), ("out", jefi_fields)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
@@ -77,6 +82,9 @@ def _load():
                                    P(jefi_grid), C.c_double, P(jefi_options), vp, vp], C.c_int),
         "jefi_slice_fingerprint": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32,
                                     P(jefi_grid), C.c_double, P(jefi_options), vp, vp], C.c_int),
+        "jefi_eval_batch": ([P(jefi_problem), C.c_int32, P(jefi_options), vp], C.c_int),
+        "jefi_autotune": ([P(jefi_problem), C.c_int32, P(jefi_options), C.c_int32, vp,
+                           P(C.c_int32), P(C.c_double)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -196,6 +204,31 @@ def jefi_slice_fingerprint(src, h: jefi_history, dt: float, nt: int, obs, t: flo
                                       C.byref(make_grid(obs)), float(t),
                                       C.byref(opt) if opt is not None else None, _ptr(fp),
                                       _stream_ptr(stream)))
+
+
+def make_problem(src, h: jefi_history, dt: float, nt: int, obs, t: float, E, B) -> jefi_problem:
+    """A jefi_problem for one batch entry (E, B: device tensors [3][n_obs])."""
+    import torch
+    dt_out = JEFI_F64 if E.dtype == torch.float64 else JEFI_F32
+    return jefi_problem(make_grid(src), h, float(dt), int(nt), make_grid(obs), float(t),
+                        jefi_fields(_ptr(E), _ptr(B), dt_out))
+
+
+def jefi_eval_batch(problems, opt: Optional[jefi_options] = None, stream=None) -> None:
+    """problems: a sequence of jefi_problem (see make_problem)."""
+    arr = (jefi_problem * len(problems))(*problems)
+    _check(lib.jefi_eval_batch(arr, len(problems), C.byref(opt) if opt is not None else None,
+                               _stream_ptr(stream)))
+
+
+def jefi_autotune(problems, opt: Optional[jefi_options] = None, reps: int = 3, stream=None):
+    """Time the launch shapes on `problems`; returns (best tile_config, ms)."""
+    arr = (jefi_problem * len(problems))(*problems)
+    best = C.c_int32(0)
+    ms = C.c_double(0.0)
+    _check(lib.jefi_autotune(arr, len(problems), C.byref(opt) if opt is not None else None,
+                             int(reps), _stream_ptr(stream), C.byref(best), C.byref(ms)))
+    return int(best.value), float(ms.value)
 
 
 def upload_history(src, hist_np, dtype: int, t0: float = 0.0, newest: Optional[int] = None,

@@ -1,15 +1,20 @@
 // libjefi C ABI: argument validation, the FP64 time prelude, launch
-// configuration and per-stream scratch.  Device work is in jefi_kernels.hip.
+// planning, per-stream scratch, batched evaluation with a graph-replayed
+// persistent launch, and the launch-shape autotuner.  Device work is in
+// jefi_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/libjefi.h"
 #include "jefi_internal.h"
@@ -81,7 +86,7 @@ long long brick_count(const jefi_grid* g, int* nbx, int* nby, int* nbz) {
 
 size_t dtype_size(int dt) { return dt == JEFI_F64 ? 8 : 4; }
 
-// The evaluation time on the logical slice axis (the same FP64 sequence the
+// The evaluation time on the logical slice axis (the FP64 sequence the
 // header documents): a = (t - t0)/dt - s_old split into a_i + a_f.
 struct TimeSplit {
   long long a_i;
@@ -109,45 +114,11 @@ jefi_status time_split(double t, double t0, double dt, long long newest, int nt,
   return JEFI_OK;
 }
 
-// Per-(device, stream) scratch for FP64 split partials.
-struct Scratch {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-std::mutex g_scratch_mu;
-std::map<std::pair<int, void*>, Scratch> g_scratch;
-
-jefi_status scratch_get(void* stream, size_t bytes, void** out) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  std::lock_guard<std::mutex> lk(g_scratch_mu);
-  Scratch& s = g_scratch[{dev, stream}];
-  if (s.bytes < bytes) {
-    if (s.ptr) {
-      e = hipStreamSynchronize((hipStream_t)stream);
-      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-      hipFree(s.ptr);
-      s.ptr = nullptr;
-      s.bytes = 0;
-    }
-    size_t want = bytes + bytes / 4;
-    e = hipMalloc(&s.ptr, want);
-    if (e != hipSuccess) {
-      s.ptr = nullptr;
-      (void)hipGetLastError();
-      return fail(JEFI_ENOMEM, "scratch allocation of %zu bytes failed", want);
-    }
-    s.bytes = want;
-  }
-  *out = s.ptr;
-  return JEFI_OK;
-}
-
 struct Resolved {
   double c;
   double screen[3];
   int precision;
+  int tile_config;
 };
 
 jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resolved* r) {
@@ -157,8 +128,11 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
   if (!std::isfinite(opt->c) || !(opt->c > 0.0)) return fail(JEFI_EINVAL, "c must be finite and > 0");
   if (opt->precision != JEFI_PREC_F64 && opt->precision != JEFI_PREC_F32_COMP)
     return fail(JEFI_EINVAL, "unknown precision %d", opt->precision);
+  if (opt->tile_config < 0 || opt->tile_config > 2)
+    return fail(JEFI_EINVAL, "tile_config %d (0 = auto, 1 = 8x8x8, 2 = 8x8x4)", opt->tile_config);
   r->c = opt->c;
   r->precision = opt->precision;
+  r->tile_config = opt->tile_config;
   for (int a = 0; a < 3; ++a) {
     if (opt->screen_set) {
       if (!std::isfinite(opt->screen[a]) || opt->screen[a] < 0.0)
@@ -171,6 +145,63 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
   return JEFI_OK;
 }
 
+// ---- launch-shape table (filled by the autotuner) --------------------------
+// Key: precision, log2 bucket of observation points per instance, log2
+// bucket of total pairs.  Value: tile_config (1 = 8x8x8, 2 = 8x8x4).
+std::mutex g_tune_mu;
+std::map<long long, int> g_tune;
+bool g_tune_loaded = false;
+
+int log2_bucket(double v) { return v < 1.0 ? 0 : (int)std::floor(std::log2(v)); }
+
+long long tune_key(int precision, double obs_per_inst, double pairs) {
+  return ((long long)precision << 16) | ((long long)log2_bucket(obs_per_inst) << 8) | log2_bucket(pairs);
+}
+
+const char* tune_path() {
+  const char* p = std::getenv("JEFI_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  long long k;
+  int v;
+  while (std::fscanf(f, "%lld %d", &k, &v) == 2)
+    if (v == 1 || v == 2) g_tune[k] = v;
+  std::fclose(f);
+}
+
+void tune_store_locked() {
+  const char* path = tune_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : g_tune) std::fprintf(f, "%lld %d\n", kv.first, kv.second);
+  std::fclose(f);
+}
+
+int lookup_tile(int precision, double obs_per_inst, double pairs) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune.find(tune_key(precision, obs_per_inst, pairs));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+// tile_z for a requested config: the tuned table first, else small
+// observation grids take the 256-thread 8x8x4 tile.
+int choose_tile_z(int tile_config, int precision, double obs_per_inst, double pairs) {
+  int cfg = tile_config;
+  if (cfg == 0) cfg = lookup_tile(precision, obs_per_inst, pairs);
+  if (cfg == 0) cfg = obs_per_inst >= 32768.0 ? 1 : 2;
+  return cfg == 1 ? 8 : 4;
+}
+
 // Box of cell centres of a grid (canonical FP64 corners).
 void grid_box(const jefi_grid* g, double lo[3], double hi[3]) {
   for (int a = 0; a < 3; ++a) {
@@ -179,44 +210,39 @@ void grid_box(const jefi_grid* g, double lo[3], double hi[3]) {
   }
 }
 
-// Launch description shared by the field evaluation and the fingerprint.
 struct Plan {
   PairParams p;
   int multi;
   bool all_dead;
+  bool empty;
 };
 
+void set_tiles(PairParams& p, const jefi_grid* obs, int tile_z) {
+  p.tile_z = tile_z;
+  p.ntx = (obs->n[0] + kTileEdge - 1) / kTileEdge;
+  p.nty = (obs->n[1] + kTileEdge - 1) / kTileEdge;
+  p.ntz = (obs->n[2] + tile_z - 1) / tile_z;
+  p.n_tiles = p.ntx * p.nty * p.ntz;
+}
+
+// Everything about a launch except the history pointer and outputs.
+// `splits_target_wg`: workgroups to aim for (single launches) or 0 to
+// leave n_splits = 1 for the caller to set.
 jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double dt, long long newest,
-                      double t0, double t, const Resolved& r, Plan* plan) {
+                      double t0, double t, const Resolved& r, int tile_z, long long splits_target_wg,
+                      Plan* plan) {
   TimeSplit ts;
   jefi_status st = time_split(t, t0, dt, newest, nt, r.c, &ts);
   if (st != JEFI_OK) return st;
   PairParams& p = plan->p;
   std::memset(&p, 0, sizeof p);
+  plan->multi = 0;
   plan->all_dead = ts.a_i <= -2;  // every pair's stencil lies before the oldest slice
   p.src = to_gd(src);
   p.obs = to_gd(obs);
   p.n_bricks = (int)brick_count(src, &p.nbx, &p.nby, &p.nbz);
-  p.ntx = (obs->n[0] + kTileEdge - 1) / kTileEdge;
-  p.nty = (obs->n[1] + kTileEdge - 1) / kTileEdge;
-  p.ntz = (obs->n[2] + kTileEdge - 1) / kTileEdge;
-  p.n_tiles = p.ntx * p.nty * p.ntz;
-  // Enough workgroups to fill 256 CUs several times over; splits of the
-  // source bricks make up what the observation tiles alone do not give.
-  const long long target_wg = 8192;
-  if (p.n_tiles == 0 || p.n_bricks == 0) {
-    plan->multi = 0;
-    return JEFI_OK;  // nothing to launch
-  }
-  long long splits = (target_wg + p.n_tiles - 1) / p.n_tiles;
-  long long max_splits = p.n_bricks / 8 > 0 ? p.n_bricks / 8 : 1;
-  if (splits > max_splits) splits = max_splits;
-  if (splits < 1) splits = 1;
-  long long bps = (p.n_bricks + splits - 1) / splits;
-  splits = (p.n_bricks + bps - 1) / bps;
-  p.n_splits = (int)splits;
-  p.bricks_per_split = (int)bps;
-  p.n_wg = (int)((long long)p.n_tiles * splits);
+  set_tiles(p, obs, tile_z);
+  plan->empty = p.n_tiles == 0 || p.n_bricks == 0;
   p.a_i = plan->all_dead ? -2 : (int)ts.a_i;
   p.a_f = ts.a_f;
   p.inv_cdt = ts.inv_cdt;
@@ -226,19 +252,25 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   p.margin = 1e-7;
   p.near_slack = 1e-12;
   p.pref = (src->spacing[0] * src->spacing[1] * src->spacing[2]) / (4.0 * M_PI);
+  p.n_splits = 1;
+  p.bricks_per_split = p.n_bricks;
+  p.n_wg = p.n_tiles;
+  if (plan->empty) return JEFI_OK;
 
   // Largest separation of any pair, and the tile/brick diagonals.
   double slo[3], shi[3], olo[3], ohi[3];
   grid_box(src, slo, shi);
   grid_box(obs, olo, ohi);
-  double rmax2 = 0.0, dt2 = 0.0, db2 = 0.0;
+  double rmax2 = 0.0, dt2 = 0.0, db2 = 0.0, hsd2 = 0.0;
   for (int a = 0; a < 3; ++a) {
     const double far = std::fmax(std::fabs(shi[a] - olo[a]), std::fabs(ohi[a] - slo[a]));
     rmax2 += far * far;
+    // the 8x8x8 tile is the widest either shape uses
     const double te = (double)std::min(obs->n[a] - 1, kTileEdge - 1) * obs->spacing[a];
     const double be = (double)std::min(src->n[a] - 1, 1) * src->spacing[a];
     dt2 += te * te;
     db2 += be * be;
+    hsd2 += src->spacing[a] * src->spacing[a];
   }
   const double rmax = std::sqrt(rmax2), diam_t = std::sqrt(dt2), diam_b = std::sqrt(db2);
   // FP32 index guard: a bound on |u32 - u64| for the FP32 sequence of the
@@ -250,10 +282,8 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   //  - u = fma(-R, 1/(c dt), a_f) with both constants rounded to FP32: u on
   //    1/(c dt), u on a_f, u on the result.
   // The band used is 1.25x that bound; a fractional part inside it sends
-  // the pair through the canonical FP64 sequence.
+  // the pair through the canonical FP64 decision.
   const double eps = std::ldexp(1.0, -24);
-  double hsd2 = 0.0;
-  for (int a = 0; a < 3; ++a) hsd2 += src->spacing[a] * src->spacing[a];
   const double e_coord = eps * (3.0 * rmax + 2.0 * diam_t + 3.0 * std::sqrt(hsd2));
   const double e_R = e_coord + 7.5 * eps * rmax;
   const double umax = ts.inv_cdt * rmax + 2.0;
@@ -265,8 +295,8 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   } else {
     // Guard-band pairs have floor(u64) in {N-1, N}, N the integer nearest
     // u32; u is monotone in r2, so floor(u64) >= N iff r2 <= T(N), with T(N)
-    // the largest FP64 r2 whose canonical u reaches N.  Kernels build the
-    // table for every N the launch can meet.
+    // the largest FP64 r2 whose canonical u reaches N.  A threshold kernel
+    // builds the table for every N the launch can meet.
     const double ulow = std::floor(ts.a_f - rmax * ts.inv_cdt) - 2.0;
     if (ulow > -1e9) {
       const long long lo = (long long)ulow;
@@ -279,13 +309,85 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
     }
   }
   p.guard = (float)g;
-  // Longest slice window any brick can need.
+  // Longest slice window any brick can need (the 8x8x8 tile bounds both shapes).
   const double wb = std::floor((diam_t + diam_b) * ts.inv_cdt * (1.0 + 1e-12) + 2.0 * p.margin + 1e-6) + 3.0;
   plan->multi = !(wb <= (double)kWmax);
+  if (plan->multi) set_tiles(p, obs, 8);  // the chunked kernel runs 8x8x8 tiles only
+
+  if (splits_target_wg > 0) {
+    long long splits = (splits_target_wg + p.n_tiles - 1) / p.n_tiles;
+    long long max_splits = p.n_bricks / 8 > 0 ? p.n_bricks / 8 : 1;
+    if (splits > max_splits) splits = max_splits;
+    if (splits < 1) splits = 1;
+    long long bps = (p.n_bricks + splits - 1) / splits;
+    splits = (p.n_bricks + bps - 1) / bps;
+    p.n_splits = (int)splits;
+    p.bricks_per_split = (int)bps;
+    p.n_wg = (int)((long long)p.n_tiles * splits);
+  }
   return JEFI_OK;
 }
 
-jefi_status check_history(const jefi_history* h, const jefi_grid* src, int nt) {
+// ---- per-(device, stream) scratch for the single-problem path ----------------
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  // threshold table last built into the head of the scratch
+  bool thr_valid = false;
+  double thr_af = 0.0, thr_icdt = 0.0;
+  int thr_lo = 0, thr_n = 0;
+};
+std::mutex g_scratch_mu;
+std::map<std::pair<int, void*>, Scratch> g_scratch;
+constexpr size_t kThrBytes = kThrMax * sizeof(double);
+
+jefi_status scratch_get(void* stream, size_t bytes, Scratch** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  Scratch& s = g_scratch[{dev, stream}];
+  if (s.bytes < bytes) {
+    if (s.ptr) {
+      e = hipStreamSynchronize((hipStream_t)stream);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      (void)hipFree(s.ptr);
+      s.ptr = nullptr;
+      s.bytes = 0;
+    }
+    const size_t want = bytes + bytes / 4;
+    e = hipMalloc(&s.ptr, want);
+    if (e != hipSuccess) {
+      s.ptr = nullptr;
+      (void)hipGetLastError();
+      return fail(JEFI_ENOMEM, "scratch allocation of %zu bytes failed", want);
+    }
+    s.bytes = want;
+    s.thr_valid = false;
+  }
+  *out = &s;
+  return JEFI_OK;
+}
+
+// Point p.thr at the scratch head and (re)build the table when the time
+// split changed since the last build on this stream.
+jefi_status prepare_thresholds(PairParams& p, Scratch* s, hipStream_t stream) {
+  if (!p.use_thr) return JEFI_OK;
+  p.thr = (double*)s->ptr;
+  if (s->thr_valid && s->thr_af == p.a_f && s->thr_icdt == p.inv_cdt && s->thr_lo == p.thr_lo &&
+      s->thr_n == p.thr_n)
+    return JEFI_OK;
+  hipError_t e = launch_thresholds(p.thr, p.thr_lo, p.thr_n, p.a_f, p.inv_cdt, stream);
+  if (e != hipSuccess) return hip_fail(e, "threshold kernel launch");
+  s->thr_valid = true;
+  s->thr_af = p.a_f;
+  s->thr_icdt = p.inv_cdt;
+  s->thr_lo = p.thr_lo;
+  s->thr_n = p.thr_n;
+  return JEFI_OK;
+}
+
+jefi_status check_history(const jefi_history* h, int nt) {
   if (!h) return fail(JEFI_EINVAL, "history is NULL");
   if (!h->data) return fail(JEFI_EINVAL, "history data is NULL");
   if (h->dtype != JEFI_F32 && h->dtype != JEFI_F64) return fail(JEFI_EINVAL, "history dtype %d", h->dtype);
@@ -295,15 +397,126 @@ jefi_status check_history(const jefi_history* h, const jefi_grid* src, int nt) {
     return fail(JEFI_EINVAL, "nt = %d must be in [1, capacity = %d]", nt, h->capacity);
   if ((long long)nt > h->newest + 1)
     return fail(JEFI_EINVAL, "nt = %d exceeds the %lld slices pushed", nt, (long long)h->newest + 1);
-  (void)src;
   return JEFI_OK;
 }
+
+// Validated single problem: everything eval needs.
+struct Checked {
+  long long ns, no;
+  Resolved r;
+  Plan plan;
+};
+
+jefi_status check_problem(const jefi_grid* src, const jefi_history* hist, double dt, int nt,
+                          const jefi_grid* obs, double t, const jefi_fields* out, const jefi_options* opt,
+                          long long splits_target_wg, int force_tile_z, Checked* c) {
+  if (!grid_ok(src, "source", &c->ns) || !grid_ok(obs, "observation", &c->no)) return JEFI_EINVAL;
+  jefi_status st = check_history(hist, nt);
+  if (st != JEFI_OK) return st;
+  if (out) {
+    if (!out->E || !out->B) return fail(JEFI_EINVAL, "output fields are NULL");
+    if (out->dtype != JEFI_F32 && out->dtype != JEFI_F64) return fail(JEFI_EINVAL, "output dtype %d", out->dtype);
+  }
+  if (!std::isfinite(dt) || !(dt > 0.0)) return fail(JEFI_EINVAL, "dt must be finite and > 0");
+  if (!std::isfinite(t)) return fail(JEFI_EINVAL, "t must be finite");
+  if ((st = resolve_options(opt, src, &c->r)) != JEFI_OK) return st;
+  const int want = c->r.precision == JEFI_PREC_F64 ? JEFI_F64 : JEFI_F32;
+  if (hist->dtype != want)
+    return fail(JEFI_EINVAL, "precision %s needs a %s history",
+                c->r.precision == JEFI_PREC_F64 ? "F64" : "F32_COMP", want == JEFI_F64 ? "F64" : "F32");
+  const int tile_z = force_tile_z ? force_tile_z
+                                  : choose_tile_z(c->r.tile_config, c->r.precision, (double)c->no,
+                                                  (double)c->no * (double)c->ns);
+  return make_plan(src, obs, nt, dt, hist->newest, hist->t0, t, c->r, tile_z, splits_target_wg, &c->plan);
+}
+
+void attach_history(PairParams& p, const jefi_history* hist, int nt) {
+  p.capacity = hist->capacity;
+  p.slot_base = (int)((hist->newest - nt + 1) % hist->capacity);
+  p.ring = hist->data;
+  p.slot_elems = (long long)p.n_bricks * kBrickCells * 4;
+}
+
+long long single_target_wg(int tile_z) { return tile_z == 8 ? 8192 : 16384; }
+
+// ---- batched evaluation ----------------------------------------------------------
+struct BatchWorkspace {
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  void* host[2] = {nullptr, nullptr};
+  size_t host_bytes = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ev_used[2] = {false, false};
+  int turn = 0;
+  // graph per (is_f64, wz), valid for the current `dev` buffer
+  std::map<int, hipGraphExec_t> graphs;
+  BatchDevice bd{};
+};
+std::mutex g_batch_mu;
+std::map<std::pair<int, void*>, BatchWorkspace> g_batch;
+
+constexpr int kBatchMaxInst = 1 << 16;
+
+void drop_graphs(BatchWorkspace& w) {
+  for (auto& kv : w.graphs) (void)hipGraphExecDestroy(kv.second);
+  w.graphs.clear();
+}
+
+int slots_per_cu(int wz) { return wz == 2 ? 2 : 4; }
+
+jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, hipGraphExec_t* out) {
+  hipGraph_t g;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  void* args[] = {&w.bd};
+  hipKernelNodeParams kp{};
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  kp.sharedMemBytes = 0;
+  hipGraphNode_t n0, n1, n2, n3;
+  kp.func = batch_reset_kernel();
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(64);
+  e = hipGraphAddKernelNode(&n0, g, nullptr, 0, &kp);
+  if (e == hipSuccess) {
+    kp.func = batch_threshold_kernel();
+    kp.gridDim = dim3(4, 256);
+    kp.blockDim = dim3(128);
+    e = hipGraphAddKernelNode(&n1, g, &n0, 1, &kp);
+  }
+  if (e == hipSuccess) {
+    kp.func = batch_pair_kernel(is_f64, wz);
+    kp.gridDim = dim3(cus * slots_per_cu(wz));
+    kp.blockDim = dim3(batch_pair_threads(wz));
+    e = hipGraphAddKernelNode(&n2, g, &n1, 1, &kp);
+  }
+  if (e == hipSuccess) {
+    kp.func = batch_epilogue_kernel();
+    kp.gridDim = dim3(2048);
+    kp.blockDim = dim3(256);
+    e = hipGraphAddKernelNode(&n3, g, &n2, 1, &kp);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_fail(e, "batch graph build");
+  return JEFI_OK;
+}
+
+struct BatchItem {
+  int inst, wg;
+  double cost;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
 extern "C" {
 
-const char* jefi_version(void) { return "libjefi 0.1 (gfx950)"; }
+const char* jefi_version(void) { return "libjefi 0.2 (gfx950)"; }
 
 const char* jefi_last_error(void) { return g_err.c_str(); }
 
@@ -330,15 +543,14 @@ jefi_status jefi_history_init(jefi_history* h, void* data, uint64_t bytes, const
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
   if (!h || !data) return fail(JEFI_EINVAL, "history or data is NULL");
   if (!std::isfinite(t0)) return fail(JEFI_EINVAL, "t0 must be finite");
-  const uint64_t need = jefi_history_bytes(src, capacity, dtype);
-  if (need == 0 && capacity >= 1) {
-    long long cells;
-    if (!grid_ok(src, "source", &cells)) return JEFI_EINVAL;
-  }
+  long long cells;
+  if (!grid_ok(src, "source", &cells)) return JEFI_EINVAL;
   if (capacity < 1 || (dtype != JEFI_F32 && dtype != JEFI_F64))
     return fail(JEFI_EINVAL, "bad capacity %d or dtype %d", capacity, dtype);
-  if (bytes < need) return fail(JEFI_EINVAL, "history buffer has %llu bytes, needs %llu",
-                                (unsigned long long)bytes, (unsigned long long)need);
+  const uint64_t need = jefi_history_bytes(src, capacity, dtype);
+  if (bytes < need)
+    return fail(JEFI_EINVAL, "history buffer has %llu bytes, needs %llu", (unsigned long long)bytes,
+                (unsigned long long)need);
   if (need > 0) {
     hipError_t e = launch_zero(data, need, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "history zero-fill launch");
@@ -377,48 +589,43 @@ jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, dou
                              const jefi_grid* obs, double t, const jefi_fields* out,
                              const jefi_options* opt, void* stream) {
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
-  long long ns = 0, no = 0;
-  if (!grid_ok(src, "source", &ns) || !grid_ok(obs, "observation", &no)) return JEFI_EINVAL;
-  jefi_status st = check_history(hist, src, nt);
-  if (st != JEFI_OK) return st;
-  if (!out || !out->E || !out->B) return fail(JEFI_EINVAL, "output fields are NULL");
-  if (out->dtype != JEFI_F32 && out->dtype != JEFI_F64) return fail(JEFI_EINVAL, "output dtype %d", out->dtype);
-  if (!std::isfinite(dt) || !(dt > 0.0)) return fail(JEFI_EINVAL, "dt must be finite and > 0");
-  if (!std::isfinite(t)) return fail(JEFI_EINVAL, "t must be finite");
-  Resolved r;
-  if ((st = resolve_options(opt, src, &r)) != JEFI_OK) return st;
-  const int want = r.precision == JEFI_PREC_F64 ? JEFI_F64 : JEFI_F32;
-  if (hist->dtype != want)
-    return fail(JEFI_EINVAL, "precision %s needs a %s history", r.precision == JEFI_PREC_F64 ? "F64" : "F32_COMP",
-                want == JEFI_F64 ? "F64" : "F32");
-  Plan plan;
-  if ((st = make_plan(src, obs, nt, dt, hist->newest, hist->t0, t, r, &plan)) != JEFI_OK) return st;
-  if (no == 0) return JEFI_OK;
+  if (!out) return fail(JEFI_EINVAL, "output fields are NULL");
+  Checked c;
+  {
+    // the split count depends on the tile shape: plan once to learn it
+    jefi_status st = check_problem(src, hist, dt, nt, obs, t, out, opt, 0, 0, &c);
+    if (st != JEFI_OK) return st;
+    const int tz = c.plan.p.tile_z;
+    st = check_problem(src, hist, dt, nt, obs, t, out, opt, single_target_wg(tz), tz, &c);
+    if (st != JEFI_OK) return st;
+  }
+  if (c.no == 0) return JEFI_OK;
   hipStream_t s = (hipStream_t)stream;
   const int out_f64 = out->dtype == JEFI_F64;
-  if (ns == 0 || plan.all_dead) {
-    hipError_t e = launch_fill_zero_fields(out->E, out->B, no, out_f64, s);
+  if (c.ns == 0 || c.plan.all_dead) {
+    hipError_t e = launch_fill_zero_fields(out->E, out->B, c.no, out_f64, s);
     return e == hipSuccess ? JEFI_OK : hip_fail(e, "zero-fill launch");
   }
-  PairParams& p = plan.p;
-  p.capacity = hist->capacity;
-  p.slot_base = (int)((hist->newest - nt + 1) % hist->capacity);
-  p.ring = hist->data;
-  p.slot_elems = (long long)p.n_bricks * kBrickCells * 4;
+  PairParams& p = c.plan.p;
+  attach_history(p, hist, nt);
   p.E = out->E;
   p.B = out->B;
   p.out_f64 = out_f64;
   p.direct = p.n_splits == 1;
-  if (!p.direct) {
-    void* scr = nullptr;
-    if ((st = scratch_get(stream, (size_t)p.n_splits * 6 * (size_t)no * sizeof(double), &scr)) != JEFI_OK)
-      return st;
-    p.partial = (double*)scr;
+  Scratch* scr = nullptr;
+  const size_t part_bytes = p.direct ? 0 : (size_t)p.n_splits * 6 * (size_t)c.no * sizeof(double);
+  jefi_status st = scratch_get(stream, kThrBytes + part_bytes, &scr);
+  if (st != JEFI_OK) return st;
+  if (!p.direct) p.partial = (double*)((char*)scr->ptr + kThrBytes);
+  if (c.r.precision == JEFI_PREC_F32_COMP && !c.plan.multi) {
+    if ((st = prepare_thresholds(p, scr, s)) != JEFI_OK) return st;
+  } else {
+    p.use_thr = 0;
   }
-  hipError_t e = launch_pairs(p, r.precision == JEFI_PREC_F64, 0, plan.multi, s);
+  hipError_t e = launch_pairs(p, c.r.precision == JEFI_PREC_F64, 0, c.plan.multi, s);
   if (e != hipSuccess) return hip_fail(e, "pair kernel launch");
   if (!p.direct) {
-    EpilogueParams ep{p.partial, p.n_splits, no, p.pref, out->E, out->B, out_f64};
+    EpilogueParams ep{p.partial, p.n_splits, c.no, p.pref, out->E, out->B, out_f64};
     e = launch_epilogue(ep, s);
     if (e != hipSuccess) return hip_fail(e, "epilogue launch");
   }
@@ -440,7 +647,7 @@ jefi_status jefi_slice_index_dump(const jefi_grid* src, int32_t nt, double dt, i
   jefi_status st = resolve_options(opt, src, &r);
   if (st != JEFI_OK) return st;
   Plan plan;
-  if ((st = make_plan(src, obs, nt, dt, newest, t0, t, r, &plan)) != JEFI_OK) return st;
+  if ((st = make_plan(src, obs, nt, dt, newest, t0, t, r, 8, 0, &plan)) != JEFI_OK) return st;
   DumpParams d;
   std::memset(&d, 0, sizeof d);
   d.src = to_gd(src);
@@ -460,31 +667,297 @@ jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* his
                                    const jefi_grid* obs, double t, const jefi_options* opt, int64_t* fp,
                                    void* stream) {
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
-  long long ns = 0, no = 0;
-  if (!grid_ok(src, "source", &ns) || !grid_ok(obs, "observation", &no)) return JEFI_EINVAL;
-  jefi_status st = check_history(hist, src, nt);
+  Checked c;
+  jefi_status st = check_problem(src, hist, dt, nt, obs, t, nullptr, opt, 0, 0, &c);
   if (st != JEFI_OK) return st;
-  if (!fp && no > 0) return fail(JEFI_EINVAL, "fp is NULL");
-  if (!std::isfinite(dt) || !(dt > 0.0) || !std::isfinite(t)) return fail(JEFI_EINVAL, "dt and t must be finite, dt > 0");
-  Resolved r;
-  if ((st = resolve_options(opt, src, &r)) != JEFI_OK) return st;
-  const int want = r.precision == JEFI_PREC_F64 ? JEFI_F64 : JEFI_F32;
-  if (hist->dtype != want) return fail(JEFI_EINVAL, "history dtype does not match the precision");
-  Plan plan;
-  if ((st = make_plan(src, obs, nt, dt, hist->newest, hist->t0, t, r, &plan)) != JEFI_OK) return st;
-  if (no == 0) return JEFI_OK;
+  const int tz = c.plan.p.tile_z;
+  if ((st = check_problem(src, hist, dt, nt, obs, t, nullptr, opt, single_target_wg(tz), tz, &c)) != JEFI_OK)
+    return st;
+  if (!fp && c.no > 0) return fail(JEFI_EINVAL, "fp is NULL");
+  if (c.no == 0) return JEFI_OK;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_zero(fp, (unsigned long long)no * 4 * sizeof(int64_t), s);
+  hipError_t e = launch_zero(fp, (unsigned long long)c.no * 4 * sizeof(int64_t), s);
   if (e != hipSuccess) return hip_fail(e, "fingerprint zero-fill");
-  if (ns == 0 || plan.all_dead) return JEFI_OK;
-  PairParams& p = plan.p;
-  p.capacity = hist->capacity;
-  p.slot_base = (int)((hist->newest - nt + 1) % hist->capacity);
-  p.ring = hist->data;
-  p.slot_elems = (long long)p.n_bricks * kBrickCells * 4;
+  if (c.ns == 0 || c.plan.all_dead) return JEFI_OK;
+  PairParams& p = c.plan.p;
+  attach_history(p, hist, nt);
   p.fp = (unsigned long long*)fp;
-  e = launch_pairs(p, r.precision == JEFI_PREC_F64, 1, plan.multi, s);
+  Scratch* scr = nullptr;
+  if ((st = scratch_get(stream, kThrBytes, &scr)) != JEFI_OK) return st;
+  if (c.r.precision == JEFI_PREC_F32_COMP && !c.plan.multi) {
+    if ((st = prepare_thresholds(p, scr, s)) != JEFI_OK) return st;
+  } else {
+    p.use_thr = 0;
+  }
+  e = launch_pairs(p, c.r.precision == JEFI_PREC_F64, 1, c.plan.multi, s);
   return e == hipSuccess ? JEFI_OK : hip_fail(e, "fingerprint kernel launch");
+}
+
+jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream) {
+  if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
+  if (n < 0 || n > kBatchMaxInst) return fail(JEFI_EINVAL, "batch of %d problems (limit %d)", n, kBatchMaxInst);
+  if (n == 0) return JEFI_OK;
+  if (!probs) return fail(JEFI_EINVAL, "problems are NULL");
+  hipStream_t s = (hipStream_t)stream;
+  // Validate everything before any device work.
+  std::vector<Checked> cs((size_t)n);
+  double obs_sum = 0.0, pair_sum = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const jefi_problem& q = probs[i];
+    jefi_status st = check_problem(&q.src, &q.hist, q.dt, q.nt, &q.obs, q.t, &q.out, opt, 0, 8, &cs[i]);
+    if (st != JEFI_OK) {
+      std::string m = g_err;
+      return fail(st, "problem %d: %s", i, m.c_str());
+    }
+    obs_sum += (double)cs[i].no;
+    pair_sum += (double)cs[i].no * (double)cs[i].ns;
+  }
+  const Resolved& r0 = cs[0].r;
+  const int is_f64 = r0.precision == JEFI_PREC_F64;
+  for (int i = 1; i < n; ++i)
+    if (cs[i].r.precision != r0.precision) return fail(JEFI_EINVAL, "mixed precisions in one batch");
+  const int tile_z = choose_tile_z(r0.tile_config, r0.precision, obs_sum / n, pair_sum);
+  const int wz = tile_z == 8 ? 2 : 1;
+
+  // Instances the persistent kernel does not take: empty, all-dead, or
+  // windows longer than one staging chunk.  They run on their own launches.
+  std::vector<int> batch_idx;
+  for (int i = 0; i < n; ++i) {
+    const jefi_problem& q = probs[i];
+    Checked& c = cs[i];
+    if (c.no == 0) continue;
+    if (c.ns == 0 || c.plan.all_dead) {
+      hipError_t e = launch_fill_zero_fields(q.out.E, q.out.B, c.no, q.out.dtype == JEFI_F64, s);
+      if (e != hipSuccess) return hip_fail(e, "zero-fill launch");
+      continue;
+    }
+    if (c.plan.multi) {
+      jefi_status st = jefi_eval_fields(&q.src, &q.hist, q.dt, q.nt, &q.obs, q.t, &q.out, opt, stream);
+      if (st != JEFI_OK) return st;
+      continue;
+    }
+    jefi_status st = make_plan(&q.src, &q.obs, q.nt, q.dt, q.hist.newest, q.hist.t0, q.t, c.r, tile_z, 0, &c.plan);
+    if (st != JEFI_OK) return st;
+    batch_idx.push_back(i);
+  }
+  const int nb = (int)batch_idx.size();
+  if (nb == 0) return JEFI_OK;
+
+  // Splits: equal-cost items, at least 4 per workgroup slot.
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int tile_pts = 64 * (tile_z == 8 ? 8 : 4);
+  double total_cost = 0.0;
+  for (int k = 0; k < nb; ++k) {
+    const PairParams& p = cs[batch_idx[k]].plan.p;
+    total_cost += (double)p.n_tiles * tile_pts * (double)p.n_bricks * kBrickCells;
+  }
+  const double target = std::max(total_cost / (4.0 * cus * slots_per_cu(wz)), 1.0);
+  std::vector<BatchItem> items;
+  std::vector<PairParams> params((size_t)nb);
+  std::vector<EpilogueParams> epi((size_t)nb);
+  std::vector<long long> prefix((size_t)nb + 1, 0);
+  size_t part_doubles = 0;
+  const int G = (is_f64 ? 1 : 2) * wz;
+  for (int k = 0; k < nb; ++k) {
+    const int i = batch_idx[k];
+    PairParams p = cs[i].plan.p;
+    const double per_tile = (double)tile_pts * (double)p.n_bricks * kBrickCells;
+    long long splits = (long long)std::ceil(per_tile / target);
+    long long max_splits = std::max(1, p.n_bricks / (4 * G));
+    splits = std::max(1LL, std::min(splits, max_splits));
+    long long bps = (p.n_bricks + splits - 1) / splits;
+    splits = (p.n_bricks + bps - 1) / bps;
+    p.n_splits = (int)splits;
+    p.bricks_per_split = (int)bps;
+    p.n_wg = p.n_tiles * p.n_splits;
+    attach_history(p, &probs[i].hist, probs[i].nt);
+    p.E = probs[i].out.E;
+    p.B = probs[i].out.B;
+    p.out_f64 = probs[i].out.dtype == JEFI_F64;
+    p.direct = p.n_splits == 1;
+    if (is_f64) p.use_thr = 0;
+    if (!p.direct) part_doubles += (size_t)p.n_splits * 6 * (size_t)cs[i].no;
+    params[k] = p;
+    const double item_cost = (double)tile_pts * (double)bps * kBrickCells;
+    for (int wg = 0; wg < p.n_wg; ++wg) items.push_back({k, wg, item_cost});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const BatchItem& a, const BatchItem& b) { return a.cost > b.cost; });
+  const int n_items = (int)items.size();
+
+  // Workspace layout (device): params | items | counts | counter | epi | prefix | thresholds | partials
+  const size_t o_params = 0;
+  const size_t o_items = align_up(o_params + sizeof(PairParams) * nb, 256);
+  const size_t o_counts = align_up(o_items + sizeof(int2) * n_items, 256);
+  const size_t o_counter = o_counts + 64;
+  const size_t o_epi = align_up(o_counter + 64, 256);
+  const size_t o_prefix = align_up(o_epi + sizeof(EpilogueParams) * nb, 256);
+  const size_t o_thr = align_up(o_prefix + sizeof(long long) * (nb + 1), 256);
+  const size_t o_part = align_up(o_thr + kThrBytes * nb, 256);
+  const size_t dev_bytes = o_part + part_doubles * sizeof(double);
+  const size_t host_bytes = o_thr;  // the uploaded head
+
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchWorkspace& w = g_batch[{dev, stream}];
+  hipError_t e;
+  if (w.dev_bytes < dev_bytes) {
+    if (w.dev) {
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+      (void)hipFree(w.dev);
+      w.dev = nullptr;
+    }
+    drop_graphs(w);
+    const size_t want = dev_bytes + dev_bytes / 4;
+    if ((e = hipMalloc(&w.dev, want)) != hipSuccess) {
+      (void)hipGetLastError();
+      w.dev = nullptr;
+      w.dev_bytes = 0;
+      return fail(JEFI_ENOMEM, "batch workspace of %zu bytes", want);
+    }
+    w.dev_bytes = want;
+  }
+  if (w.host_bytes < host_bytes) {
+    for (int b = 0; b < 2; ++b) {
+      if (w.ev_used[b]) (void)hipEventSynchronize(w.ev[b]);
+      if (w.host[b]) (void)hipHostFree(w.host[b]);
+      w.host[b] = nullptr;
+    }
+    const size_t want = host_bytes + host_bytes / 4;
+    for (int b = 0; b < 2; ++b) {
+      if ((e = hipHostMalloc(&w.host[b], want, hipHostMallocDefault)) != hipSuccess) {
+        (void)hipGetLastError();
+        w.host_bytes = 0;
+        return fail(JEFI_ENOMEM, "pinned staging of %zu bytes", want);
+      }
+    }
+    w.host_bytes = want;
+  }
+  for (int b = 0; b < 2; ++b)
+    if (!w.ev[b] && (e = hipEventCreateWithFlags(&w.ev[b], hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+  char* dbase = (char*)w.dev;
+  for (int k = 0; k < nb; ++k) {
+    PairParams& p = params[k];
+    if (p.use_thr) p.thr = (double*)(dbase + o_thr + kThrBytes * k);
+  }
+  size_t part_at = 0;
+  for (int k = 0; k < nb; ++k) {
+    PairParams& p = params[k];
+    const long long no = (long long)p.obs.n[0] * p.obs.n[1] * p.obs.n[2];
+    if (!p.direct) {
+      p.partial = (double*)(dbase + o_part) + part_at;
+      epi[k] = EpilogueParams{p.partial, p.n_splits, no, p.pref, p.E, p.B, p.out_f64};
+      part_at += (size_t)p.n_splits * 6 * (size_t)no;
+      prefix[k + 1] = prefix[k] + 6 * no;
+    } else {
+      epi[k] = EpilogueParams{nullptr, 0, no > 0 ? no : 1, p.pref, p.E, p.B, p.out_f64};
+      prefix[k + 1] = prefix[k];
+    }
+  }
+  // Stage the head in pinned memory (wait until its previous upload finished).
+  const int b = w.turn;
+  w.turn ^= 1;
+  if (w.ev_used[b] && (e = hipEventSynchronize(w.ev[b])) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  char* hb = (char*)w.host[b];
+  std::memcpy(hb + o_params, params.data(), sizeof(PairParams) * nb);
+  int2* hi = (int2*)(hb + o_items);
+  for (int q = 0; q < n_items; ++q) hi[q] = make_int2(items[q].inst, items[q].wg);
+  int* hc = (int*)(hb + o_counts);
+  hc[0] = n_items;
+  hc[1] = nb;
+  std::memcpy(hb + o_epi, epi.data(), sizeof(EpilogueParams) * nb);
+  std::memcpy(hb + o_prefix, prefix.data(), sizeof(long long) * (nb + 1));
+  if ((e = hipMemcpyAsync(w.dev, hb, host_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
+    return hip_fail(e, "batch descriptor upload");
+  if ((e = hipEventRecord(w.ev[b], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  w.ev_used[b] = true;
+  // Graph of reset -> thresholds -> persistent pairs -> epilogue, pointer
+  // arguments only: rebuilt only when the workspace moves.
+  BatchDevice bd;
+  bd.params = (const PairParams*)(dbase + o_params);
+  bd.items = (const int2*)(dbase + o_items);
+  bd.counts = (const int*)(dbase + o_counts);
+  bd.counter = (int*)(dbase + o_counter);
+  bd.epi = (const EpilogueParams*)(dbase + o_epi);
+  bd.epi_prefix = (const long long*)(dbase + o_prefix);
+  if (std::memcmp(&bd, &w.bd, sizeof bd) != 0) {
+    drop_graphs(w);
+    w.bd = bd;
+  }
+  const int gkey = is_f64 * 4 + wz;
+  auto it = w.graphs.find(gkey);
+  if (it == w.graphs.end()) {
+    hipGraphExec_t ge;
+    jefi_status st = build_graph(w, is_f64, wz, &ge);
+    if (st != JEFI_OK) return st;
+    it = w.graphs.emplace(gkey, ge).first;
+  }
+  if ((e = hipGraphLaunch(it->second, s)) != hipSuccess) return hip_fail(e, "batch graph launch");
+  return JEFI_OK;
+}
+
+jefi_status jefi_autotune(const jefi_problem* probs, int32_t n, const jefi_options* opt, int32_t reps,
+                          void* stream, int32_t* best_config, double* best_ms) {
+  if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
+  if (!probs || n < 1) return fail(JEFI_EINVAL, "autotune needs at least one problem");
+  if (reps < 1) reps = 3;
+  jefi_options o;
+  if (opt)
+    o = *opt;
+  else
+    jefi_options_default(&o);
+  double obs_sum = 0.0, pair_sum = 0.0;
+  for (int i = 0; i < n; ++i) {
+    long long ns = 0, no = 0;
+    if (!grid_ok(&probs[i].src, "source", &ns) || !grid_ok(&probs[i].obs, "observation", &no)) return JEFI_EINVAL;
+    obs_sum += (double)no;
+    pair_sum += (double)no * (double)ns;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  int best = 0;
+  double best_t = 0.0;
+  jefi_status st = JEFI_OK;
+  for (int cfg = 1; cfg <= 2 && st == JEFI_OK; ++cfg) {
+    o.tile_config = cfg;
+    auto run = [&]() {
+      return n == 1 ? jefi_eval_fields(&probs[0].src, &probs[0].hist, probs[0].dt, probs[0].nt, &probs[0].obs,
+                                       probs[0].t, &probs[0].out, &o, stream)
+                    : jefi_eval_batch(probs, n, &o, stream);
+    };
+    if ((st = run()) != JEFI_OK) break;  // warm-up (also builds graphs)
+    (void)hipEventRecord(e0, s);
+    for (int q = 0; q < reps && st == JEFI_OK; ++q) st = run();
+    (void)hipEventRecord(e1, s);
+    if (st != JEFI_OK) break;
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+      st = hip_fail(e, "hipEventSynchronize");
+      break;
+    }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    const double per = (double)ms / reps;
+    if (best == 0 || per < best_t) {
+      best = cfg;
+      best_t = per;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != JEFI_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[tune_key(o.precision, obs_sum / n, pair_sum)] = best;
+    tune_store_locked();
+  }
+  if (best_config) *best_config = best;
+  if (best_ms) *best_ms = best_t;
+  return JEFI_OK;
 }
 
 }  // extern "C"

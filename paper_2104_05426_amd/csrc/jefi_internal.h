@@ -48,6 +48,8 @@ struct PairParams {
   int use_thr;           // 1: decide guard-band pairs by the r2 threshold table
   int thr_lo;            // table covers floor positions thr_lo .. thr_lo + thr_n - 1
   int thr_n;
+  double* thr;           // device table of thr_n thresholds (filled by the threshold kernel)
+  int tile_z;            // observation tile edge in z: 8 (512 threads) or 4 (256 threads)
   const void* ring;      // device ring, library layout
   long long slot_elems;  // elements (of the ring dtype) per slot
   double* partial;       // FP64 [n_splits][6][n_obs] (unscaled sums)
@@ -69,6 +71,16 @@ struct EpilogueParams {
   int out_f64;
 };
 
+// Batched launch: per-instance parameters and work items live in device memory.
+struct BatchDevice {
+  const PairParams* params;   // [n_inst]
+  const int2* items;          // [n_items] (instance, workgroup id within the instance)
+  const int* counts;          // counts[0] = n_items, counts[1] = n_inst
+  int* counter;               // work-queue head
+  const EpilogueParams* epi;  // [n_inst] (n_splits == 0 for instances written directly)
+  const long long* epi_prefix;  // [n_inst + 1] cumulative 6 * n_obs of instances with an epilogue
+};
+
 struct DumpParams {
   GridD src, obs;
   int a_i;
@@ -86,6 +98,13 @@ hipError_t launch_ingest(const void* slice, void* slot, const GridD& src, int nb
                          int is_f64, hipStream_t s);
 hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk,
                         hipStream_t s);
+hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt, hipStream_t s);
+// Kernel entry points of a batched evaluation, for graph nodes.
+void* batch_reset_kernel();
+void* batch_threshold_kernel();
+void* batch_pair_kernel(int is_f64, int wz);
+void* batch_epilogue_kernel();
+int batch_pair_threads(int wz);
 hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);
 hipError_t launch_fill_zero_fields(void* E, void* B, long long n_obs, int out_f64, hipStream_t s);
 hipError_t launch_dump(const DumpParams& p, hipStream_t s);

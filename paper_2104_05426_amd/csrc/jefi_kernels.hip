@@ -160,10 +160,10 @@ __device__ __forceinline__ TileGeom tile_geom(const PairParams& p, int tile) {
   const int tz = tile / (p.ntx * p.nty);
   g.ix0 = tx * kTileEdge;
   g.iy0 = ty * kTileEdge;
-  g.iz0 = tz * kTileEdge;
+  g.iz0 = tz * p.tile_z;
   g.ix1 = min(g.ix0 + kTileEdge - 1, p.obs.n[0] - 1);
   g.iy1 = min(g.iy0 + kTileEdge - 1, p.obs.n[1] - 1);
-  g.iz1 = min(g.iz0 + kTileEdge - 1, p.obs.n[2] - 1);
+  g.iz1 = min(g.iz0 + p.tile_z - 1, p.obs.n[2] - 1);
   g.refx = canon(p.obs.o[0], g.ix0, p.obs.h[0]);
   g.refy = canon(p.obs.o[1], g.iy0, p.obs.h[1]);
   g.refz = canon(p.obs.o[2], g.iz0, p.obs.h[2]);
@@ -714,30 +714,40 @@ struct FpAcc {
   }
 };
 
-template <typename T, int G, bool FP>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
+template <typename T, int WZ>
+struct FastShape {
+  static constexpr int G = (sizeof(T) == 4 ? 2 : 1) * WZ;  // bricks per round
+  static constexpr int KT = 256 * WZ;                      // threads
+  static constexpr int NPL = Traits<T>::kPlanes;
+  static constexpr int PU = G * kBrickCells * kCellStride;  // 16-byte units per plane
+  static constexpr int THR = sizeof(T) == 4 ? kThrMax : 1;
+};
+
+// One workgroup's share of a launch: tile x source split number `bid` of
+// the problem described by p.
+template <typename T, int WZ, bool FP>
+__device__ __forceinline__ void pair_body(const PairParams& p, int bid,
+                                          float4 (&lds)[FastShape<T, WZ>::NPL * FastShape<T, WZ>::PU],
+                                          int4 (&tab_i)[2][FastShape<T, WZ>::G],
+                                          float4 (&tab_f)[2][FastShape<T, WZ>::G],
+                                          double (&tab_c)[2][FastShape<T, WZ>::G][6],
+                                          double (&thr)[FastShape<T, WZ>::THR]) {
   using Raw = typename RawOf<T>::type;
-  constexpr int NPL = Traits<T>::kPlanes;
-  constexpr int CELLS = G * kBrickCells;
-  constexpr int PU = CELLS * kCellStride;
+  constexpr int G = FastShape<T, WZ>::G;
+  constexpr int kThreads = FastShape<T, WZ>::KT;
+  constexpr int PU = FastShape<T, WZ>::PU;
   constexpr int EPT = G * kBrickCells * kWmax / kThreads;  // staged entries per thread
   constexpr int NRAW = EPT + 2;
   constexpr int NQ = kWmax / EPT;
   static_assert(EPT >= 1 && EPT * kThreads == G * kBrickCells * kWmax, "staging map");
-  __shared__ float4 lds[NPL * PU];
-  __shared__ int4 tab_i[2][G];
-  __shared__ float4 tab_f[2][G];
-  __shared__ double tab_c[2][G][6];
-  __shared__ double thr[sizeof(T) == 4 ? kThrMax : 1];
 
-  const int bid = xcd_remap((int)blockIdx.x, p.n_wg);
   const int split = bid / p.n_tiles;
   const int tile = bid - split * p.n_tiles;
   const TileGeom tg = tile_geom(p, tile);
   const int t = (int)threadIdx.x;
   if constexpr (sizeof(T) == 4) {
     if (p.use_thr)
-      for (int i = t; i < p.thr_n; i += kThreads) thr[i] = r2_threshold(p.thr_lo + i, p.a_f, p.inv_cdt);
+      for (int i = t; i < p.thr_n; i += kThreads) thr[i] = p.thr[i];
   }
   const int w = t >> 6, l = t & 63;
   const int ix = tg.ix0 + (w & 1) * 4 + (l & 3);
@@ -1007,6 +1017,88 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   }
 }
 
+template <typename T, int WZ, bool FP>
+__global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
+  using S = FastShape<T, WZ>;
+  __shared__ float4 lds[S::NPL * S::PU];
+  __shared__ int4 tab_i[2][S::G];
+  __shared__ float4 tab_f[2][S::G];
+  __shared__ double tab_c[2][S::G][6];
+  __shared__ double thr[S::THR];
+  pair_body<T, WZ, FP>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr);
+}
+
+// Persistent batched launch: workgroups pull (instance, workgroup id) items
+// from a queue ordered heaviest first until it is empty.
+template <typename T, int WZ>
+__global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_persistent(BatchDevice bd) {
+  using S = FastShape<T, WZ>;
+  __shared__ float4 lds[S::NPL * S::PU];
+  __shared__ int4 tab_i[2][S::G];
+  __shared__ float4 tab_f[2][S::G];
+  __shared__ double tab_c[2][S::G][6];
+  __shared__ double thr[S::THR];
+  __shared__ int cur;
+  const int n_items = bd.counts[0];
+  for (;;) {
+    __syncthreads();  // the previous item is done with LDS and `cur`
+    if (threadIdx.x == 0) cur = atomicAdd(bd.counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(cur);
+    if (it >= n_items) break;
+    const int2 item = bd.items[it];
+    const int inst = __builtin_amdgcn_readfirstlane(item.x);
+    const int bid = __builtin_amdgcn_readfirstlane(item.y);
+    pair_body<T, WZ, false>(bd.params[inst], bid, lds, tab_i, tab_f, tab_c, thr);
+  }
+}
+
+__global__ void threshold_kernel(double* out, int lo, int n, double af, double icdt) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) out[i] = r2_threshold(lo + i, af, icdt);
+}
+
+__global__ void batch_threshold(BatchDevice bd) {
+  const int n_inst = bd.counts[1];
+  for (int inst = (int)blockIdx.y; inst < n_inst; inst += (int)gridDim.y) {
+    const PairParams& p = bd.params[inst];
+    if (!p.use_thr) continue;
+    for (int i = (int)(blockIdx.x * blockDim.x + threadIdx.x); i < p.thr_n; i += (int)(gridDim.x * blockDim.x))
+      p.thr[i] = r2_threshold(p.thr_lo + i, p.a_f, p.inv_cdt);
+  }
+}
+
+__global__ void batch_reset(BatchDevice bd) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *bd.counter = 0;
+}
+
+// Fixed-order split reduction for every instance of a batch that has splits.
+__global__ void batch_epilogue(BatchDevice bd) {
+  const int n_inst = bd.counts[1];
+  const long long total = bd.epi_prefix[n_inst];
+  for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {  // last instance whose prefix is <= g
+      const int mid = (lo + hi + 1) >> 1;
+      if (bd.epi_prefix[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    const EpilogueParams& ep = bd.epi[lo];
+    const long long local = g - bd.epi_prefix[lo];
+    const long long comp = local / ep.n_obs;
+    const long long o = local - comp * ep.n_obs;
+    double s = 0.0;
+    for (int q = 0; q < ep.n_splits; ++q) s += ep.partial[((long long)q * 6 + comp) * ep.n_obs + o];
+    const double v = s * ep.pref;
+    void* dst = comp < 3 ? ep.E : ep.B;
+    const long long at = (comp % 3) * ep.n_obs + o;
+    if (ep.out_f64)
+      ((double*)dst)[at] = v;
+    else
+      ((float*)dst)[at] = (float)v;
+  }
+}
+
 __global__ void epilogue_kernel(EpilogueParams p) {
   const long long total = p.n_obs * 6;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -1157,12 +1249,21 @@ hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int mu
   dim3 grid(p.n_wg), block(kThreads);
 #define JEFI_LAUNCH(T, G, FPM, MUL) \
   hipLaunchKernelGGL((pair_kernel<T, G, FPM, MUL>), grid, block, 0, s, p)
-#define JEFI_FAST(T, G, FPM) hipLaunchKernelGGL((pair_kernel_fast<T, G, FPM>), grid, block, 0, s, p)
+#define JEFI_FAST(T, WZ, FPM) \
+  hipLaunchKernelGGL((pair_kernel_fast<T, WZ, FPM>), grid, dim3(256 * WZ), 0, s, p)
   if (!multi_chunk) {
-    if (is_f64) {
-      if (fingerprint) JEFI_FAST(double, 2, true); else JEFI_FAST(double, 2, false);
+    if (p.tile_z == 8) {
+      if (is_f64) {
+        if (fingerprint) JEFI_FAST(double, 2, true); else JEFI_FAST(double, 2, false);
+      } else {
+        if (fingerprint) JEFI_FAST(float, 2, true); else JEFI_FAST(float, 2, false);
+      }
     } else {
-      if (fingerprint) JEFI_FAST(float, 4, true); else JEFI_FAST(float, 4, false);
+      if (is_f64) {
+        if (fingerprint) JEFI_FAST(double, 1, true); else JEFI_FAST(double, 1, false);
+      } else {
+        if (fingerprint) JEFI_FAST(float, 1, true); else JEFI_FAST(float, 1, false);
+      }
     }
     return hipGetLastError();
   }
@@ -1183,6 +1284,21 @@ hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int mu
 #undef JEFI_FAST
   return hipGetLastError();
 }
+
+hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(threshold_kernel, dim3((n + 127) / 128), dim3(128), 0, s, out, lo, n, af, icdt);
+  return hipGetLastError();
+}
+
+void* batch_reset_kernel() { return (void*)batch_reset; }
+void* batch_threshold_kernel() { return (void*)batch_threshold; }
+void* batch_epilogue_kernel() { return (void*)batch_epilogue; }
+void* batch_pair_kernel(int is_f64, int wz) {
+  if (is_f64) return wz == 2 ? (void*)pair_kernel_persistent<double, 2> : (void*)pair_kernel_persistent<double, 1>;
+  return wz == 2 ? (void*)pair_kernel_persistent<float, 2> : (void*)pair_kernel_persistent<float, 1>;
+}
+int batch_pair_threads(int wz) { return 256 * wz; }
 
 hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s) {
   if (p.n_obs == 0) return hipSuccess;

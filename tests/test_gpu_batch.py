@@ -1,0 +1,129 @@
+"""Batched persistent evaluation: every problem of an uneven batch gives
+the same fields as its own single launch (and as the oracle on sampled
+points), for both launch shapes and both precisions; graph replays agree;
+instances the persistent kernel leaves out (empty, wholly-past, long
+windows) still come out right; the autotuner picks a valid shape."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.compare import rel_l2
+from workloads import Blob, Grid, Problem, blob_history, centred_grid
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+SOLO = {"f64": 1e-13, "f32": 2e-6}
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests import _gpu as G
+    return G
+
+
+def _small_batch(count=12, seed=31):
+    """Uneven instances drawn like the batch workload, at sizes the oracle
+    samples quickly: source edge 4..24, observation edge 3..28."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        es = int(rng.integers(4, 25))
+        eo = int(rng.integers(3, 29))
+        dx = 1.6 / es
+        dt = dx / 2.0
+        nt = 2 * es + 8
+        src = centred_grid((es, es, es), dx)
+        m = (es - eo) // 2
+        obs = Grid((eo, eo, eo), tuple(src.origin[a] + m * dx for a in range(3)), (dx, dx, dx))
+        blobs = workloads.draw_blobs(rng, int(rng.integers(1, 8)), (-0.8, 0.8))
+        hist = blob_history(src, blobs, nt, dt)
+        out.append(Problem(f"b{i}", src, obs, hist, dt, (nt - 1) * dt, 0.0, nt - 1, 1.0,
+                           workloads.default_screen(src)))
+    return out
+
+
+def _check_against(results, refs, tol, label):
+    for k, ((Eg, Bg), (Er, Br)) in enumerate(zip(results, refs)):
+        e, _ = rel_l2(Eg, Er)
+        b, _ = rel_l2(Bg, Br)
+        assert np.all(np.isfinite(Eg)) and np.all(np.isfinite(Bg)), (label, k)
+        assert max(e + b) <= tol, (label, k, e, b)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("tile", [1, 2])
+def test_batch_equals_solo_and_oracle(prec, tile):
+    G = _gpu()
+    probs = _small_batch()
+    run = G.BatchRun(probs, prec)
+    solo = run.run_solo(tile)
+    batch = run.run_batch(tile)
+    _check_against(batch, solo, SOLO[prec], f"batch vs solo {prec} tile {tile}")
+    rng = np.random.default_rng(9)
+    for k, p in enumerate(probs):
+        sel = np.sort(rng.choice(p.obs.size, size=min(24, p.obs.size), replace=False))
+        Er, Br = oracle.eval_problem(p, sel=sel)
+        _check_against([(batch[k][0][:, sel], batch[k][1][:, sel])], [(Er, Br)], TOL[prec],
+                       f"batch vs oracle {prec} tile {tile} #{k}")
+    print(f"batch of {len(probs)} ({prec}, tile {tile}) matches solo and oracle", flush=True)
+
+
+def test_graph_replays_agree():
+    """Several replays of the captured launch sequence, with eager work and
+    synchronisations in between, each equal to the first."""
+    import torch
+    G = _gpu()
+    probs = _small_batch(8, seed=4)
+    run = G.BatchRun(probs, "f32")
+    first = run.run_batch()
+    for r in range(4):
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        again = run.run_batch()
+        for (a, b), (c, d) in zip(first, again):
+            assert np.array_equal(a, c) and np.array_equal(b, d), r
+        del junk
+
+
+def test_batch_with_fallback_instances():
+    """An empty observation grid, an evaluation time before every stencil
+    and a long-window instance (dt << spacing) inside one batch."""
+    G = _gpu()
+    probs = _small_batch(4, seed=8)
+    base = probs[0]
+    probs.append(Problem("empty-obs", base.src, Grid((0, 0, 0), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)),
+                         base.hist, base.dt, base.t, 0.0, base.newest, 1.0, base.screen))
+    probs.append(Problem("past", base.src, base.obs, base.hist, base.dt, -5.0, 0.0, base.newest, 1.0,
+                         base.screen))
+    src = centred_grid((6, 5, 7), 0.1)
+    dt = 0.01
+    nt = 100
+    hist = blob_history(src, [Blob(1.0, 0.15, (0.0, 0.05, 0.0), (0.3, 0.0, 0.2))], nt, dt)
+    probs.append(Problem("long-window", src, src.shifted_cells(3, 1, -2), hist, dt, (nt - 1) * dt, 0.0,
+                         nt - 1, 1.0, workloads.default_screen(src)))
+    run = G.BatchRun(probs, "f32")
+    batch = run.run_batch()
+    for k, p in enumerate(probs):
+        if p.obs.size == 0:
+            continue
+        Er, Br = oracle.eval_problem(p)
+        if p.name == "past":
+            assert np.all(batch[k][0] == 0.0) and np.all(batch[k][1] == 0.0)
+            continue
+        _check_against([batch[k]], [(Er, Br)], TOL["f32"], p.name)
+
+
+def test_autotune_picks_a_shape(tmp_path, monkeypatch):
+    G = _gpu()
+    probs = _small_batch(6, seed=12)
+    run = G.BatchRun(probs, "f32")
+    best, ms = run.J.jefi_autotune(run.problem_structs(), run.options(0), reps=2)
+    assert best in (1, 2) and ms > 0.0
+    # the tuned choice now drives tile_config = 0 and still gives correct fields
+    batch = run.run_batch(0)
+    solo = run.run_solo(best)
+    _check_against(batch, solo, SOLO["f32"], "tuned")

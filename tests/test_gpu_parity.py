@@ -64,13 +64,14 @@ def _assert_fields(Eg, Bg, Er, Br, tol, label=""):
     assert max(e + b) <= tol, (e, b)
 
 
+@pytest.mark.parametrize("tile", [1, 2])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_tiny_fields(prec):
+def test_tiny_fields(prec, tile):
     G = _gpu()
     p = workloads.config_tiny()
     Er, Br = oracle.eval_problem(p)
-    Eg, Bg = G.gpu_eval(p, prec)
-    _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"tiny {prec}")
+    Eg, Bg = G.gpu_eval(p, prec, tile=tile)
+    _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"tiny {prec} tile {tile}")
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -85,15 +86,16 @@ def test_tiny_slice_index_bit_exact(prec):
     assert np.array_equal(fp, fp_ref)
 
 
+@pytest.mark.parametrize("tile", [1, 2])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_medium_fields_and_fingerprint(prec):
+def test_medium_fields_and_fingerprint(prec, tile):
     G = _gpu()
     p = _medium()
     Er, Br = _oracle(p)
-    Eg, Bg = G.gpu_eval(p, prec)
-    _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"medium {prec}")
+    Eg, Bg = G.gpu_eval(p, prec, tile=tile)
+    _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"medium {prec} tile {tile}")
     fp_ref = _oracle(p, kind="fp")
-    fp = G.gpu_fingerprint(p, prec)
+    fp = G.gpu_fingerprint(p, prec, tile=tile)
     assert np.array_equal(fp, fp_ref)
 
 
@@ -143,11 +145,12 @@ def test_ragged_random_problems(seed):
     G = _gpu()
     p = _ragged_problem(seed)
     Er, Br = oracle.eval_problem(p)
+    fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
     for prec in ["f64", "f32"]:
-        Eg, Bg = G.gpu_eval(p, prec)
-        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"{p.name} {prec}")
-        fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
-        assert np.array_equal(G.gpu_fingerprint(p, prec), fp_ref)
+        for tile in [1, 2]:
+            Eg, Bg = G.gpu_eval(p, prec, tile=tile)
+            _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"{p.name} {prec} tile {tile}")
+            assert np.array_equal(G.gpu_fingerprint(p, prec, tile=tile), fp_ref)
 
 
 @pytest.mark.parametrize("seed", range(4))
