@@ -179,6 +179,92 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
 jefi_status jefi_autotune(const jefi_problem* probs, int32_t n, const jefi_options* opt, int32_t reps,
                           void* stream, int32_t* best_config, double* best_ms);
 
+/* ---- serving loop (row: serving) -----------------------------------------
+ * Field evaluations of many sessions (a time-stepping source each) arrive at
+ * any time.  Each session keeps its history resident in a caller-provided
+ * device arena (the HBM budget); each request pushes the session's next
+ * slice and evaluates on its own observation grid.  A scheduler thread
+ * admits requests in arrival order as arena bytes and batch slots free up
+ * (evicting idle sessions least-recently-used first and re-uploading their
+ * history from a host copy when they return) and launches them as batched
+ * evaluations on several streams, so new arrivals start while earlier
+ * batches still run (continuous batching).  One request per session is on
+ * the device at a time; a session's requests run in submission order.
+ * Per-request timestamps give latency percentiles.  The per-stream batch
+ * workspace (descriptor tables, split partials) lies outside the arena. */
+typedef struct jefi_server jefi_server;
+
+typedef struct {
+  void* arena;              /* DEVICE memory the server may use (histories, slices, outputs) */
+  uint64_t arena_bytes;
+  uint64_t pinned_bytes;    /* host staging pool (0 = 256 MiB) */
+  int32_t precision;        /* jefi_precision of every evaluation */
+  int32_t max_inflight;     /* batches on the device at once, 1..8 (0 = 2) */
+  int32_t max_batch;        /* requests per batch (0 = 256) */
+  int32_t max_queue;        /* waiting requests before submit returns EBUSY (0 = 65536) */
+} jefi_server_config;
+
+typedef struct {
+  uint64_t session;
+  const void* new_slice;    /* HOST [4][n_src] (float for F32_COMP, double for F64), or NULL;
+                               copied before submit returns; pushed as the next step */
+  jefi_grid obs;
+  double t;                 /* NaN = the time of the newest step after the push */
+  void* E;                  /* outputs [3][n_obs] of out_dtype: HOST memory when */
+  void* B;                  /*   out_on_host, else DEVICE memory; valid once done */
+  int32_t out_dtype;
+  int32_t out_on_host;
+} jefi_request;
+
+typedef struct {
+  int32_t status;           /* JEFI_PENDING, JEFI_OK or the request's error */
+  int32_t batch_size;       /* requests in the batch it ran in */
+  uint64_t t_submit_ns, t_admit_ns, t_start_ns, t_done_ns;  /* CLOCK_MONOTONIC */
+  uint64_t pairs;           /* n_src * n_obs */
+} jefi_result;
+
+typedef struct {
+  uint64_t submitted, completed, failed, batches, max_batch;
+  uint64_t evictions, rematerialisations;
+  uint64_t arena_bytes, arena_used, arena_high_water;
+  uint64_t pairs;
+} jefi_server_stats;
+
+/* Start a server on the current device.  EINVAL on a bad config, ENOMEM
+ * when the pinned pool cannot be allocated. */
+jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out);
+
+/* A session: source grid, ring capacity, evaluation window (slices used,
+ * 1 <= window <= capacity), time axis (step s at t0 + s*dt), and optionally
+ * its first init_nt steps (HOST [init_nt][4][n_src], oldest first).
+ * EINVAL for a used id or bad sizes; ETOOLARGE when the ring can never fit
+ * the arena. */
+jefi_status jefi_server_open_session(jefi_server* sv, uint64_t session, const jefi_grid* src, int32_t capacity,
+                                     int32_t window, double t0, double dt, const void* init_history,
+                                     int32_t init_nt);
+
+/* Non-blocking.  ENOENT: unknown session; EBUSY: queue full (retry);
+ * ETOOLARGE: the request can never fit the arena or the pinned pool;
+ * EINVAL: bad grid or outputs.  A request whose time lies after its
+ * session's newest step fails with EINVAL when it is admitted. */
+jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t* ticket);
+
+/* JEFI_PENDING while running; once done returns the request's status (the
+ * ticket is then released), res filled either way.  ENOENT: unknown ticket. */
+jefi_status jefi_server_poll(jefi_server* sv, uint64_t ticket, jefi_result* res);
+
+/* Blocks until the ticket is done (one waiter per ticket), then as poll. */
+jefi_status jefi_server_wait(jefi_server* sv, uint64_t ticket, jefi_result* res);
+
+/* Frees an idle session's ring.  EBUSY while it has queued or running requests. */
+jefi_status jefi_server_close_session(jefi_server* sv, uint64_t session);
+
+jefi_status jefi_server_get_stats(jefi_server* sv, jefi_server_stats* out);
+
+/* Runs every queued request to completion, then stops and frees the
+ * server; returns JEFI_EDEVICE if a device failure occurred. */
+jefi_status jefi_server_destroy(jefi_server* sv);
+
 /* ---- slice-decision diagnostics ------------------------------------------
  * The integer decisions the field kernels take, exposed for bit-exact
  * checks against an independent implementation. */

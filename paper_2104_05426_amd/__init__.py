@@ -29,6 +29,8 @@ EXPORTS = [
     "jefi_version", "jefi_last_error", "jefi_options_default", "jefi_history_bytes",
     "jefi_history_init", "jefi_history_push", "jefi_eval_fields", "jefi_slice_index_dump",
     "jefi_slice_fingerprint", "jefi_eval_batch", "jefi_autotune",
+    "jefi_server_create", "jefi_server_open_session", "jefi_server_submit", "jefi_server_poll",
+    "jefi_server_wait", "jefi_server_close_session", "jefi_server_get_stats", "jefi_server_destroy",
 ]
 
 
@@ -61,6 +63,29 @@ class jefi_problem(C.Structure):
                 ("obs", jefi_grid), ("t", C.c_double), ("out", jefi_fields)]
 
 
+class jefi_server_config(C.Structure):
+    _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("pinned_bytes", C.c_uint64),
+                ("precision", C.c_int32), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
+                ("max_queue", C.c_int32)]
+
+
+class jefi_request(C.Structure):
+    _fields_ = [("session", C.c_uint64), ("new_slice", C.c_void_p), ("obs", jefi_grid), ("t", C.c_double),
+                ("E", C.c_void_p), ("B", C.c_void_p), ("out_dtype", C.c_int32), ("out_on_host", C.c_int32)]
+
+
+class jefi_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batch_size", C.c_int32), ("t_submit_ns", C.c_uint64),
+                ("t_admit_ns", C.c_uint64), ("t_start_ns", C.c_uint64), ("t_done_ns", C.c_uint64),
+                ("pairs", C.c_uint64)]
+
+
+class jefi_server_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "failed", "batches", "max_batch",
+                                         "evictions", "rematerialisations", "arena_bytes", "arena_used",
+                                         "arena_high_water", "pairs")]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() or "
@@ -85,6 +110,15 @@ def _load():
         "jefi_eval_batch": ([P(jefi_problem), C.c_int32, P(jefi_options), vp], C.c_int),
         "jefi_autotune": ([P(jefi_problem), C.c_int32, P(jefi_options), C.c_int32, vp,
                            P(C.c_int32), P(C.c_double)], C.c_int),
+        "jefi_server_create": ([P(jefi_server_config), P(vp)], C.c_int),
+        "jefi_server_open_session": ([vp, C.c_uint64, P(jefi_grid), C.c_int32, C.c_int32, C.c_double,
+                                      C.c_double, vp, C.c_int32], C.c_int),
+        "jefi_server_submit": ([vp, P(jefi_request), P(C.c_uint64)], C.c_int),
+        "jefi_server_poll": ([vp, C.c_uint64, P(jefi_result)], C.c_int),
+        "jefi_server_wait": ([vp, C.c_uint64, P(jefi_result)], C.c_int),
+        "jefi_server_close_session": ([vp, C.c_uint64], C.c_int),
+        "jefi_server_get_stats": ([vp, P(jefi_server_stats)], C.c_int),
+        "jefi_server_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -249,3 +283,76 @@ def upload_history(src, hist_np, dtype: int, t0: float = 0.0, newest: Optional[i
         sl = torch.as_tensor(hist_np[j], dtype=tdt).to(device).contiguous()
         jefi_history_push(h, src, sl, stream)
     return store, h
+
+
+class Server:
+    """Thin owner of a jefi_server handle (the C calls do all the work).
+    ``arena``: a device tensor whose bytes the server may use."""
+
+    def __init__(self, arena, precision=JEFI_PREC_F32_COMP, max_inflight=2, max_batch=256,
+                 max_queue=65536, pinned_bytes=0):
+        self.arena = arena
+        cfg = jefi_server_config(_ptr(arena), arena.numel() * arena.element_size(), int(pinned_bytes),
+                                 int(precision), int(max_inflight), int(max_batch), int(max_queue))
+        h = C.c_void_p()
+        _check(lib.jefi_server_create(C.byref(cfg), C.byref(h)))
+        self.h = h
+        self.precision = precision
+
+    def open_session(self, session, src, capacity, window, t0, dt, init_history=None):
+        """init_history: numpy [init_nt][4][n_src] in the server's precision (or None)."""
+        import numpy as np
+        ptr, nt = None, 0
+        if init_history is not None:
+            arr = np.ascontiguousarray(init_history,
+                                       dtype=np.float64 if self.precision == JEFI_PREC_F64 else np.float32)
+            ptr, nt = arr.ctypes.data, int(arr.shape[0])
+        _check(lib.jefi_server_open_session(self.h, int(session), C.byref(make_grid(src)), int(capacity),
+                                            int(window), float(t0), float(dt), ptr, nt))
+
+    def submit(self, session, obs, E, B, new_slice=None, t=float("nan"), out_on_host=True):
+        """E, B: numpy arrays [3][n_obs] (out_on_host) or device tensors;
+        new_slice: numpy [4][n_src] in the server's precision or None.
+        Returns (status, ticket); the caller keeps E/B alive until done."""
+        import numpy as np
+        if out_on_host:
+            eptr, bptr = E.ctypes.data, B.ctypes.data
+            odt = JEFI_F64 if E.dtype == np.float64 else JEFI_F32
+        else:
+            import torch
+            eptr, bptr = _ptr(E), _ptr(B)
+            odt = JEFI_F64 if E.dtype == torch.float64 else JEFI_F32
+        sl = None
+        if new_slice is not None:
+            sl = np.ascontiguousarray(new_slice,
+                                      dtype=np.float64 if self.precision == JEFI_PREC_F64 else np.float32)
+        rq = jefi_request(int(session), sl.ctypes.data if sl is not None else None, make_grid(obs), float(t),
+                          eptr, bptr, odt, 1 if out_on_host else 0)
+        tk = C.c_uint64(0)
+        st = lib.jefi_server_submit(self.h, C.byref(rq), C.byref(tk))
+        return st, int(tk.value)
+
+    def poll(self, ticket):
+        res = jefi_result()
+        st = lib.jefi_server_poll(self.h, int(ticket), C.byref(res))
+        return st, res
+
+    def wait(self, ticket):
+        res = jefi_result()
+        st = lib.jefi_server_wait(self.h, int(ticket), C.byref(res))
+        return st, res
+
+    def close_session(self, session):
+        return lib.jefi_server_close_session(self.h, int(session))
+
+    def stats(self):
+        out = jefi_server_stats()
+        _check(lib.jefi_server_get_stats(self.h, C.byref(out)))
+        return {n: int(getattr(out, n)) for n, _ in jefi_server_stats._fields_}
+
+    def destroy(self):
+        if self.h is not None:
+            st = lib.jefi_server_destroy(self.h)
+            self.h = None
+            return st
+        return JEFI_OK

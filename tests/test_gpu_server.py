@@ -1,0 +1,173 @@
+"""Serving loop on the GPU: every request's result equals the same
+evaluation run alone (a fresh ring holding that session's window, one
+jefi_eval_fields launch), also when the arena is too small for all sessions
+and sessions are evicted and brought back; bad requests fail cleanly."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.compare import rel_l2
+from workloads import Grid, Problem, blob_history, centred_grid
+
+pytestmark = pytest.mark.gpu
+
+SOLO_TOL = 2e-6   # FP32 batched vs FP32 alone (different split sums)
+ORACLE_TOL = 1e-5
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2104_05426_amd as J
+    return J
+
+
+def _sessions(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(count):
+        es = int(rng.integers(5, 17))
+        dx = 1.6 / es
+        cap = 2 * es + 8
+        window = cap
+        blobs = workloads.draw_blobs(rng, int(rng.integers(1, 6)), (-0.8, 0.8))
+        src = centred_grid((es, es, es), dx)
+        out.append(dict(id=100 + s, src=src, dx=dx, dt=dx / 2, cap=cap, window=window, blobs=blobs))
+    return out
+
+
+def _obs_for(sess, rng):
+    eo = int(rng.integers(3, 19))
+    dx = sess["dx"]
+    m = (sess["src"].n[0] - eo) // 2
+    return Grid((eo, eo, eo), tuple(sess["src"].origin[a] + m * dx for a in range(3)), (dx, dx, dx))
+
+
+def _solo(J, src, hist_window, dt, newest, obs, t):
+    """One evaluation alone: a ring holding exactly the window."""
+    import torch
+    store, h = J.upload_history(src, hist_window, J.JEFI_F32, t0=0.0, newest=newest)
+    E = torch.empty((3, max(obs.size, 1)), dtype=torch.float32, device="cuda")
+    B = torch.empty_like(E)
+    J.jefi_eval_fields(src, h, dt, hist_window.shape[0], obs, t, E[:, :obs.size], B[:, :obs.size])
+    torch.cuda.synchronize()
+    return E[:, :obs.size].double().cpu().numpy(), B[:, :obs.size].double().cpu().numpy()
+
+
+def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6):
+    import torch
+    rng = np.random.default_rng(seed)
+    sess = _sessions(n_sessions, seed)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    sv = J.Server(arena, precision=J.JEFI_PREC_F32_COMP, max_inflight=2, max_batch=64)
+    full = {}
+    for s in sess:
+        steps = init_steps + n_req  # enough slices for every push
+        full[s["id"]] = blob_history(s["src"], s["blobs"], steps, s["dt"])
+        sv.open_session(s["id"], s["src"], s["cap"], s["window"], 0.0, s["dt"],
+                        full[s["id"]][:init_steps].astype(np.float32))
+    newest = {s["id"]: init_steps - 1 for s in sess}
+    reqs = []
+    for q in range(n_req):
+        s = sess[int(rng.integers(0, n_sessions))]
+        sid = s["id"]
+        newest[sid] += 1
+        obs = _obs_for(s, rng)
+        E = np.full((3, obs.size), np.nan, dtype=np.float32)
+        B = np.full((3, obs.size), np.nan, dtype=np.float32)
+        st, tk = sv.submit(sid, obs, E, B, new_slice=full[sid][newest[sid]].astype(np.float32))
+        assert st == J.JEFI_OK, J.jefi_last_error()
+        reqs.append(dict(ticket=tk, sid=sid, newest=newest[sid], obs=obs, E=E, B=B, s=s))
+    results = []
+    for r in reqs:
+        st, res = sv.wait(r["ticket"])
+        assert st == J.JEFI_OK and res.status == J.JEFI_OK, (st, res.status)
+        results.append(res)
+    stats = sv.stats()
+    assert sv.destroy() == J.JEFI_OK
+    return reqs, results, stats, full
+
+
+def _check_solo(J, reqs, full, n_oracle=4):
+    rng = np.random.default_rng(1)
+    for i, r in enumerate(reqs):
+        s = r["s"]
+        nt = min(s["window"], r["newest"] + 1)
+        window = full[r["sid"]][r["newest"] - nt + 1:r["newest"] + 1].astype(np.float32).astype(np.float64)
+        t = r["newest"] * s["dt"]
+        Es, Bs = _solo(J, s["src"], window, s["dt"], r["newest"], r["obs"], t)
+        e, _ = rel_l2(r["E"].astype(np.float64), Es)
+        b, _ = rel_l2(r["B"].astype(np.float64), Bs)
+        assert max(e + b) <= SOLO_TOL, (i, e, b)
+        if i < n_oracle:
+            p = Problem("srv", s["src"], r["obs"], window, s["dt"], t, 0.0, r["newest"], 1.0,
+                        workloads.default_screen(s["src"]))
+            Er, Br = oracle.eval_problem(p)
+            e, _ = rel_l2(r["E"].astype(np.float64), Er)
+            b, _ = rel_l2(r["B"].astype(np.float64), Br)
+            assert max(e + b) <= ORACLE_TOL, (i, e, b)
+
+
+def test_server_results_equal_solo_in_the_mix():
+    J = _gpu()
+    reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=6, n_req=60, seed=3)
+    assert stats["completed"] == 60 and stats["failed"] == 0
+    assert stats["batches"] >= 1
+    print(f"server: {stats['batches']} batches, largest {stats['max_batch']}", flush=True)
+    # requests were batched together (continuous batching, not one by one)
+    assert max(r.batch_size for r in results) > 1
+    for r in results:
+        assert r.t_submit_ns <= r.t_admit_ns <= r.t_start_ns <= r.t_done_ns
+    _check_solo(J, reqs, full)
+
+
+def test_server_evicts_and_rematerialises():
+    """An arena that holds only a few session rings at once."""
+    J = _gpu()
+    sess = _sessions(6, 5)
+    ring = max(J.jefi_history_bytes(s["src"], s["cap"], J.JEFI_F32) for s in sess)
+    arena = int(ring * 2.5) + (4 << 20)
+    reqs, results, stats, full = _run_stream(J, arena, n_sessions=6, n_req=40, seed=5)
+    print(f"evictions {stats['evictions']} rematerialisations {stats['rematerialisations']}", flush=True)
+    assert stats["evictions"] > 0 and stats["rematerialisations"] > 0
+    assert stats["arena_high_water"] <= arena
+    _check_solo(J, reqs, full, n_oracle=2)
+
+
+def test_server_rejections():
+    import torch
+    J = _gpu()
+    arena = torch.empty(8 << 20, dtype=torch.uint8, device="cuda")
+    sv = J.Server(arena)
+    src = centred_grid((6, 6, 6), 0.1)
+    h0 = blob_history(src, workloads.draw_blobs(np.random.default_rng(0), 2, (-0.3, 0.3)), 4, 0.05)
+    sv.open_session(7, src, 12, 12, 0.0, 0.05, h0.astype(np.float32))
+    obs = centred_grid((4, 4, 4), 0.1)
+    E = np.zeros((3, obs.size), np.float32)
+    B = np.zeros((3, obs.size), np.float32)
+    st, _ = sv.submit(99, obs, E, B)
+    assert st == J.JEFI_ENOENT
+    big = centred_grid((200, 200, 200), 0.01)
+    Eb = np.zeros((3, 1), np.float32)
+    st, _ = sv.submit(7, big, Eb, Eb)
+    assert st == J.JEFI_ETOOLARGE
+    # a time after the newest step fails at admission
+    st, tk = sv.submit(7, obs, E, B, t=10.0)
+    assert st == J.JEFI_OK
+    st, res = sv.wait(tk)
+    assert res.status == J.JEFI_EINVAL
+    # a valid request still runs afterwards
+    st, tk = sv.submit(7, obs, E, B)
+    st, res = sv.wait(tk)
+    assert res.status == J.JEFI_OK and np.all(np.isfinite(E))
+    assert sv.close_session(7) == J.JEFI_OK
+    st, _ = sv.submit(7, obs, E, B)
+    assert st == J.JEFI_ENOENT
+    with pytest.raises(J.JefiError):
+        sv.open_session(8, centred_grid((300, 300, 300), 0.01), 64, 64, 0.0, 0.005)
+    assert sv.destroy() == J.JEFI_OK
