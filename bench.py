@@ -118,6 +118,258 @@ def run_path(p, extra, prec, steps, warmup):
     return out
 
 
+def run_batch_workload(args):
+    """64 uneven instances: one push per instance and one batched persistent
+    evaluation per step, against one launch per instance (FP32 and FP64)."""
+    import torch
+    import workloads
+    import oracle
+    import paper_2104_05426_amd as J
+    from oracle.compare import max_rel_l2
+    probs = workloads.batch_instances(64, seed=3)
+    K, W = args.steps, args.warmup
+    pairs = sum(p.pairs for p in probs)
+    log(f"batch: {len(probs)} instances, {pairs:.3e} pairs per evaluation")
+    extras = [workloads.blob_history(p.src, p.blobs, list(range(p.newest + 1, p.newest + 1 + W + K)), p.dt)
+              for p in probs]
+
+    def setup(prec):
+        hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        rings = [J.upload_history(p.src, p.hist, hdt, t0=p.t0, newest=p.newest, capacity=p.nt) for p in probs]
+        sl = [[torch.as_tensor(x[i], dtype=tdt).cuda() for i in range(x.shape[0])] for x in extras]
+        outs = [(torch.empty((3, p.obs.size), device="cuda"), torch.empty((3, p.obs.size), device="cuda"))
+                for p in probs]
+        opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP)
+        return rings, sl, outs, opt
+
+    def timed(prec, batched, steps):
+        rings, sl, outs, opt = setup(prec)
+
+        def step(i):
+            for (st, h), p, x in zip(rings, probs, sl):
+                J.jefi_history_push(h, p.src, x[i])
+            if batched:
+                J.jefi_eval_batch([J.make_problem(p.src, h, p.dt, p.nt, p.obs, p.t0 + h.newest * p.dt, E, B)
+                                   for (st, h), p, (E, B) in zip(rings, probs, outs)], opt)
+            else:
+                for (st, h), p, (E, B) in zip(rings, probs, outs):
+                    J.jefi_eval_fields(p.src, h, p.dt, p.nt, p.obs, p.t0 + h.newest * p.dt, E, B, opt)
+        for i in range(W):
+            step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(W + i)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t0
+        res = [(E.double().cpu().numpy(), B.double().cpu().numpy()) for E, B in outs]
+        newest = [h.newest for st, h in rings]
+        return dt_ / steps, res, newest
+
+    tb, res_b, newest = timed("f32", True, K)
+    log(f"batched f32: {tb*1e3:.2f} ms/step")
+    ts, res_s, _ = timed("f32", False, K)
+    log(f"per-instance f32: {ts*1e3:.2f} ms/step")
+    t64, res_64, _ = timed("f64", False, max(2, K // 2))
+    log(f"per-instance f64: {t64*1e3:.2f} ms/step")
+    t64b, _, _ = timed("f64", True, max(2, K // 2))
+    log(f"batched f64: {t64b*1e3:.2f} ms/step")
+    # parity: batched FP32 against the per-instance FP64 results, and sampled oracle points
+    worst_vs64 = max(max_rel_l2(Eb, Bb, E6, B6) for (Eb, Bb), (E6, B6) in zip(res_b, res_64))
+    rng = np.random.default_rng(4)
+    worst_or = 0.0
+    for k in rng.choice(len(probs), size=6, replace=False):
+        p = probs[k]
+        full = np.concatenate([p.hist, extras[k]], axis=0)
+        last = newest[k]
+        win = full[last - p.nt + 1:last + 1]
+        sel = np.sort(rng.choice(p.obs.size, size=min(16, p.obs.size), replace=False))
+        Er, Br = oracle.eval_fields(p.src, p.obs, win, p.dt, p.t0 + last * p.dt, p.t0, last, p.c, p.screen, sel=sel)
+        worst_or = max(worst_or, max_rel_l2(res_b[k][0][:, sel], res_b[k][1][:, sel], Er, Br))
+    return {
+        "metric": METRIC, "value": round(pairs / tb / 1e9, 3), "unit": "G pairs/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(tb * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch: 64 independent problems, source edge {8..40}, observation edge {8..48}, "
+                               "history 2 e_s + 8, 1-30 Gaussian blobs each; one slice pushed per instance and "
+                               "one persistent batched launch per step",
+                   "pairs_per_step": pairs},
+        "per_instance_f32": {"value": round(pairs / ts / 1e9, 3), "ms_per_step": round(ts * 1e3, 3)},
+        "per_instance_f64": {"value": round(pairs / t64 / 1e9, 3), "ms_per_step": round(t64 * 1e3, 3)},
+        "batched_f64": {"value": round(pairs / t64b / 1e9, 3), "ms_per_step": round(t64b * 1e3, 3)},
+        "batched_over_per_instance_f32": round(ts / tb, 3),
+        "parity": {"max_rel_l2_vs_fp64_path": float(f"{worst_vs64:.3e}"),
+                   "max_rel_l2_vs_oracle_sampled": float(f"{worst_or:.3e}"), "tol": 1e-5,
+                   "ok": bool(worst_vs64 <= 1e-5 and worst_or <= 1e-5)},
+    }
+
+
+def run_serve_workload(args):
+    """Poisson request stream over 128 sessions through the serving loop
+    (real-time replay for latency, back-to-back for peak throughput), and the
+    one-launch-per-request FP64 path on the same requests."""
+    import threading
+    import torch
+    import workloads
+    import oracle
+    import paper_2104_05426_amd as J
+    from oracle.compare import max_rel_l2
+    specs, reqs = workloads.serving_trace(rate=200.0, duration=args.serve_seconds, sessions=128, seed=5)
+    log(f"serve: {len(reqs)} requests over {args.serve_seconds:.0f} s, {len(specs)} sessions")
+    grids, hist0, slices, obs_of = {}, {}, [], []
+    next_step = {}
+    for sp in specs:
+        es, dx = sp["edge"], sp["dx"]
+        grids[sp["session"]] = workloads.centred_grid((es, es, es), dx)
+        hist0[sp["session"]] = workloads.blob_history(grids[sp["session"]], sp["blobs"], sp["capacity"], sp["dt"])
+        next_step[sp["session"]] = sp["capacity"]
+    steps_of = []
+    for r in reqs:
+        sp = specs[r["session"]]
+        g = grids[r["session"]]
+        st = next_step[r["session"]]
+        next_step[r["session"]] += 1
+        steps_of.append(st)
+        slices.append(workloads.blob_history(g, sp["blobs"], [st], sp["dt"])[0])
+        eo = r["obs_edge"]
+        m = (sp["edge"] - eo) // 2
+        obs_of.append(workloads.Grid((eo, eo, eo), tuple(g.origin[a] + m * sp["dx"] for a in range(3)),
+                                     (sp["dx"],) * 3))
+    pairs = np.array([grids[r["session"]].size * obs_of[i].size for i, r in enumerate(reqs)], dtype=np.float64)
+    log(f"serve: inputs ready, {pairs.sum():.3e} pairs in total")
+    rng_s = np.random.default_rng(6)
+    keep_fp64 = set(range(0, len(reqs), max(1, len(reqs) // 200)))
+    keep_oracle = set(int(v) for v in rng_s.choice(len(reqs), size=4, replace=False))
+    keep = keep_fp64 | keep_oracle
+    free = torch.cuda.mem_get_info()[0]
+    arena_bytes = int(min(200e9, 0.6 * free))
+
+    def serve(paced):
+        arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+        sv = J.Server(arena, precision=J.JEFI_PREC_F32_COMP, max_inflight=2, max_batch=256)
+        for sp in specs:
+            sv.open_session(sp["session"], grids[sp["session"]], sp["capacity"], sp["capacity"], 0.0, sp["dt"],
+                            hist0[sp["session"]].astype(np.float32))
+        outs = [None] * len(reqs)
+        tickets = [None] * len(reqs)
+        lat = np.zeros(len(reqs))
+        bsz = np.zeros(len(reqs))
+        done_evt = threading.Event()
+
+        def waiter():
+            for i in range(len(reqs)):
+                while tickets[i] is None:
+                    time.sleep(0.0002)
+                st, res = sv.wait(tickets[i])
+                assert res.status == J.JEFI_OK, (i, res.status)
+                lat[i] = (res.t_done_ns - res.t_submit_ns) / 1e6
+                bsz[i] = res.batch_size
+                if i not in keep:
+                    outs[i] = None
+            done_evt.set()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            if paced:
+                delay = r["arrival"] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+            E = np.empty((3, obs_of[i].size), np.float32)
+            B = np.empty((3, obs_of[i].size), np.float32)
+            outs[i] = (E, B)
+            while True:
+                st, tk = sv.submit(r["session"], obs_of[i], E, B, new_slice=slices[i].astype(np.float32))
+                if st != J.JEFI_EBUSY:
+                    break
+                time.sleep(0.0005)
+            assert st == J.JEFI_OK, (i, st, J.jefi_last_error())
+            tickets[i] = tk
+            if i % 2000 == 0:
+                log(f"  submitted {i}")
+        done_evt.wait()
+        wall = time.perf_counter() - t0
+        th.join()
+        stats = sv.stats()
+        sv.destroy()
+        del arena
+        return wall, lat, bsz, outs, stats
+
+    wall_p, lat_p, bsz_p, outs_p, stats_p = serve(paced=True)
+    log(f"paced: {len(reqs)/wall_p:.1f} req/s, p50 {np.percentile(lat_p, 50):.2f} ms p99 {np.percentile(lat_p, 99):.2f} ms")
+    wall_o, lat_o, bsz_o, outs_o, stats_o = serve(paced=False)
+    log(f"back-to-back: {len(reqs)/wall_o:.1f} req/s")
+
+    # one FP64 launch per request, in arrival order, back to back
+    rings = {}
+    for sp in specs:
+        rings[sp["session"]] = J.upload_history(grids[sp["session"]], hist0[sp["session"]], J.JEFI_F64,
+                                                capacity=sp["capacity"])
+    opt64 = J.jefi_options_default(precision=J.JEFI_PREC_F64)
+    res64 = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        sp = specs[r["session"]]
+        store, h = rings[r["session"]]
+        g = grids[r["session"]]
+        J.jefi_history_push(h, g, torch.as_tensor(slices[i], dtype=torch.float64).cuda())
+        E = torch.empty((3, obs_of[i].size), dtype=torch.float64, device="cuda")
+        B = torch.empty_like(E)
+        J.jefi_eval_fields(g, h, sp["dt"], sp["capacity"], obs_of[i], h.newest * sp["dt"], E, B, opt64)
+        out = (E.cpu().numpy(), B.cpu().numpy())  # copy back + sync, as a client would
+        res64.append(out if i in keep else None)
+        if i % 2000 == 0:
+            log(f"  fp64 baseline {i}")
+    wall64 = time.perf_counter() - t0
+    log(f"fp64 one-launch-per-request: {len(reqs)/wall64:.1f} req/s")
+    worst = 0.0
+    for i in sorted(keep_fp64):
+        worst = max(worst, max_rel_l2(outs_p[i][0].astype(np.float64), outs_p[i][1].astype(np.float64),
+                                      res64[i][0], res64[i][1]))
+    # a few requests against the oracle
+    worst_or = 0.0
+    rng = np.random.default_rng(7)
+    for i in sorted(keep_oracle):
+        r = reqs[i]
+        sp = specs[r["session"]]
+        g = grids[r["session"]]
+        cap = sp["capacity"]
+        st = steps_of[i]
+        win = workloads.blob_history(g, sp["blobs"], list(range(st - cap + 1, st + 1)), sp["dt"])
+        sel = np.sort(rng.choice(obs_of[i].size, size=min(16, obs_of[i].size), replace=False))
+        Er, Br = oracle.eval_fields(g, obs_of[i], win, sp["dt"], st * sp["dt"], 0.0, st, 1.0, None, sel=sel)
+        worst_or = max(worst_or, max_rel_l2(outs_p[i][0][:, sel].astype(np.float64),
+                                            outs_p[i][1][:, sel].astype(np.float64), Er, Br))
+    total_pairs = float(pairs.sum())
+    return {
+        "metric": METRIC, "value": round(total_pairs / wall_o / 1e9, 3), "unit": "G pairs/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": round(wall_o * 1e3 / len(reqs), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serve: Poisson 200 req/s for {args.serve_seconds:.0f} s over 128 sessions "
+                               "(source edge log-U[8,48], observation edge log-U[8,64], ring 2 e_s + 8, one "
+                               "new slice per request), HBM arena budget "
+                               f"{arena_bytes/1e9:.0f} GB, FP32-compensated",
+                   "requests": len(reqs)},
+        "served_req_per_s_back_to_back": round(len(reqs) / wall_o, 2),
+        "paced": {"req_per_s": round(len(reqs) / wall_p, 2),
+                  "latency_ms": {"p50": round(float(np.percentile(lat_p, 50)), 3),
+                                 "p99": round(float(np.percentile(lat_p, 99)), 3),
+                                 "max": round(float(lat_p.max()), 3)},
+                  "mean_batch": round(float(bsz_p.mean()), 2), "batches": stats_p["batches"]},
+        "back_to_back_latency_ms": {"p50": round(float(np.percentile(lat_o, 50)), 3),
+                                    "p99": round(float(np.percentile(lat_o, 99)), 3)},
+        "fp64_one_launch_per_request": {"req_per_s": round(len(reqs) / wall64, 2),
+                                        "value": round(total_pairs / wall64 / 1e9, 3)},
+        "server_over_fp64_baseline": round(wall64 / wall_o, 3),
+        "parity": {"max_rel_l2_vs_fp64_sampled": float(f"{worst:.3e}"),
+                   "max_rel_l2_vs_oracle_sampled": float(f"{worst_or:.3e}"), "tol": 1e-5,
+                   "ok": bool(worst <= 1e-5 and worst_or <= 1e-5)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +380,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the request stream for --workload serve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (a known-size "
                          "reference for the HBM byte counters)")
@@ -152,6 +406,13 @@ def main():
         torch.cuda.synchronize()
         log(f"copy probe: {n * 4} bytes read and written")
         del a, b
+
+    if args.workload == "batch":
+        print(json.dumps(run_batch_workload(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(run_serve_workload(args)), flush=True)
+        return
 
     p = make_workload(args.workload)
     K, W = args.steps, args.warmup
