@@ -225,7 +225,8 @@ typedef struct {
 
 typedef struct {
   uint64_t submitted, completed, failed, batches, max_batch;
-  uint64_t evictions, rematerialisations;
+  uint64_t evictions;          /* idle rings dropped from the arena to make room */
+  uint64_t rematerialisations; /* rings brought back from their host shadow after an eviction */
   uint64_t arena_bytes, arena_used, arena_high_water;
   uint64_t pairs;
 } jefi_server_stats;
@@ -244,7 +245,9 @@ jefi_status jefi_server_open_session(jefi_server* sv, uint64_t session, const je
                                      int32_t init_nt);
 
 /* Non-blocking.  ENOENT: unknown session; EBUSY: queue full (retry);
- * ETOOLARGE: the request can never fit the arena or the pinned pool;
+ * ETOOLARGE: the request can never fit the arena or the pinned pool (its
+ * worst case holds the ring, the staged host shadow, the slice and the
+ * outputs at once);
  * EINVAL: bad grid or outputs.  A request whose time lies after its
  * session's newest step fails with EINVAL when it is admitted. */
 jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t* ticket);

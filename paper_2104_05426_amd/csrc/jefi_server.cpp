@@ -53,6 +53,7 @@ struct Session {
   int64_t newest = -1;
   std::vector<unsigned char> shadow;  // host copy [capacity][4][n_src], slot = step % capacity
   bool resident = false;
+  bool evicted = false;  // left the arena at least once since it was opened
   uint64_t ring_off = 0, ring_bytes = 0;
   int busy = 0;      // requests admitted and not finished
   int queued = 0;    // requests submitted and not admitted
@@ -145,6 +146,7 @@ bool make_room(jefi_server* sv, uint64_t bytes, const std::unordered_set<uint64_
     if (!victim) return false;
     sv->darena.release(victim->ring_off, victim->ring_bytes);
     victim->resident = false;
+    victim->evicted = true;
     sv->stats.evictions++;
   }
   return true;
@@ -193,7 +195,7 @@ jefi_status materialise(jefi_server* sv, Session& s, hipStream_t st, Batch& b,
       rc = jefi_history_push(&h, &s.src, sv->dbase + so + slot * slice_bytes, st);
       if (rc != JEFI_OK) return rc;
     }
-    sv->stats.rematerialisations++;
+    if (s.evicted) sv->stats.rematerialisations++;
   }
   return JEFI_OK;
 }
@@ -528,12 +530,14 @@ jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t
   if ((int)sv->queue.size() >= sv->cfg.max_queue) return JEFI_EBUSY;
   const size_t slice_bytes = (size_t)4 * s.n_src * s.elem;
   const uint64_t out_bytes = rq->out_on_host ? (uint64_t)6 * n_obs * (rq->out_dtype == JEFI_F64 ? 8 : 4) : 0;
-  uint64_t need = Arena::round_up(s.ring_bytes) + Arena::round_up(out_bytes);
+  // Worst case for one request on an otherwise empty arena: the ring, the
+  // staging of its host shadow (when it has to be brought back), the slice
+  // and the outputs, all held until its batch completes.
+  const uint64_t shadow_bytes = Arena::round_up(s.shadow.size());
+  uint64_t need = Arena::round_up(s.ring_bytes) + shadow_bytes + Arena::round_up(out_bytes);
   if (rq->new_slice) need += Arena::round_up(slice_bytes);
-  const uint64_t pin_need = Arena::round_up(rq->new_slice ? slice_bytes : 0) + out_bytes;
-  if (need > sv->cfg.arena_bytes || pin_need > sv->cfg.pinned_bytes ||
-      Arena::round_up(s.shadow.size()) > sv->cfg.pinned_bytes)
-    return JEFI_ETOOLARGE;
+  const uint64_t pin_need = shadow_bytes + Arena::round_up(rq->new_slice ? slice_bytes : 0) + out_bytes;
+  if (need > sv->cfg.arena_bytes || pin_need > sv->cfg.pinned_bytes) return JEFI_ETOOLARGE;
   Req r;
   r.ticket = sv->next_ticket++;
   r.session = rq->session;
