@@ -171,9 +171,9 @@ def run_batch_workload(args):
     log(f"batched f32: {tb*1e3:.2f} ms/step")
     ts, res_s, _ = timed("f32", False, K)
     log(f"per-instance f32: {ts*1e3:.2f} ms/step")
-    t64, res_64, _ = timed("f64", False, max(2, K // 2))
+    t64, res_64, _ = timed("f64", False, K)  # same steps: same newest slice as the FP32 runs
     log(f"per-instance f64: {t64*1e3:.2f} ms/step")
-    t64b, _, _ = timed("f64", True, max(2, K // 2))
+    t64b, _, _ = timed("f64", True, K)
     log(f"batched f64: {t64b*1e3:.2f} ms/step")
     # parity: batched FP32 against the per-instance FP64 results, and sampled oracle points
     worst_vs64 = max(max_rel_l2(Eb, Bb, E6, B6) for (Eb, Bb), (E6, B6) in zip(res_b, res_64))

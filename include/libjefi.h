@@ -102,11 +102,21 @@ typedef struct {
   double screen[3];      /* screening half-widths, used when screen_set != 0 */
   int32_t screen_set;    /* 0: half the source spacing per axis (default) */
   int32_t precision;     /* jefi_precision (default JEFI_PREC_F32_COMP) */
-  uint32_t flags;        /* reserved, 0 */
+  uint32_t flags;        /* 0 or one JEFI_FLAG_INDEX_* value; other bits are rejected */
   int32_t tile_config;   /* launch shape: 0 = automatic (autotuned table, else a size
                             heuristic), 1 = 8x8x8 observation tiles (512 threads),
                             2 = 8x8x4 tiles (256 threads) */
 } jefi_options;
+
+/* How the FP32 path reaches the canonical FP64 slice index of each pair
+ * (both give the same indices and results; only speed differs).  Default:
+ * chosen per call from the expected share of pairs within the FP32 rounding
+ * band of an integer retarded position (large on aligned grids whose
+ * spacing is a multiple of c*dt). */
+enum {
+  JEFI_FLAG_INDEX_GUARD = 1, /* decide in FP32, redo in FP64 only inside the guard band */
+  JEFI_FLAG_INDEX_TABLE = 2  /* decide every pair by its FP64 r2 against a threshold table */
+};
 
 const char* jefi_version(void);
 const char* jefi_last_error(void);

@@ -119,6 +119,7 @@ struct Resolved {
   double screen[3];
   int precision;
   int tile_config;
+  unsigned flags;
 };
 
 jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resolved* r) {
@@ -130,6 +131,9 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
     return fail(JEFI_EINVAL, "unknown precision %d", opt->precision);
   if (opt->tile_config < 0 || opt->tile_config > 2)
     return fail(JEFI_EINVAL, "tile_config %d (0 = auto, 1 = 8x8x8, 2 = 8x8x4)", opt->tile_config);
+  if (opt->flags != 0 && opt->flags != JEFI_FLAG_INDEX_GUARD && opt->flags != JEFI_FLAG_INDEX_TABLE)
+    return fail(JEFI_EINVAL, "flags 0x%x (0, JEFI_FLAG_INDEX_GUARD or JEFI_FLAG_INDEX_TABLE)", opt->flags);
+  r->flags = opt->flags;
   r->c = opt->c;
   r->precision = opt->precision;
   r->tile_config = opt->tile_config;
@@ -225,6 +229,39 @@ void set_tiles(PairParams& p, const jefi_grid* obs, int tile_z) {
   p.n_tiles = p.ntx * p.nty * p.ntz;
 }
 
+// Whether so many pairs fall in the FP32 guard band that nearly every
+// (wavefront, brick) step would take the FP64 fix-up anyway; then the pair
+// kernels decide every pair by the threshold table instead.  Aligned grids
+// whose spacing is a multiple of c*dt put a few percent of all pairs at
+// exact integer positions; generic grids put about 2g of them in the band.
+// Estimated on 2048 pairs drawn by a fixed LCG: the cost of both schemes
+// breaks even when a 512-pair step holds a guard pair with probability 1/2,
+// i.e. at about 1.4e-3 of the pairs.
+bool guard_pairs_common(const jefi_grid* src, const jefi_grid* obs, const TimeSplit& ts, double g) {
+  const long long ns = (long long)src->n[0] * src->n[1] * src->n[2];
+  const long long no = (long long)obs->n[0] * obs->n[1] * obs->n[2];
+  if (ns <= 0 || no <= 0) return false;
+  unsigned long long st = 0x9e3779b97f4a7c15ull;
+  auto next = [&st](long long n) {
+    st = st * 6364136223846793005ull + 1442695040888963407ull;
+    return (long long)((st >> 17) % (unsigned long long)n);
+  };
+  const int kSamples = 2048;
+  int hits = 0;
+  for (int q = 0; q < kSamples; ++q) {
+    const long long o = next(no), s = next(ns);
+    const long long oi[3] = {o % obs->n[0], (o / obs->n[0]) % obs->n[1], o / ((long long)obs->n[0] * obs->n[1])};
+    const long long si[3] = {s % src->n[0], (s / src->n[0]) % src->n[1], s / ((long long)src->n[0] * src->n[1])};
+    double d[3];
+    for (int a = 0; a < 3; ++a)
+      d[a] = (obs->origin[a] + (double)oi[a] * obs->spacing[a]) - (src->origin[a] + (double)si[a] * src->spacing[a]);
+    const double u = ts.a_f - std::sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]) * ts.inv_cdt;
+    const double fr = u - std::floor(u);
+    if (std::fabs(fr - 0.5) > 0.5 - g) ++hits;
+  }
+  return hits * 700 >= kSamples;  // about 1.4e-3
+}
+
 // Everything about a launch except the history pointer and outputs.
 // `splits_target_wg`: workgroups to aim for (single launches) or 0 to
 // leave n_splits = 1 for the caller to set.
@@ -309,6 +346,9 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
     }
   }
   p.guard = (float)g;
+  p.exact_idx = 0;
+  if (p.use_thr && r.flags != JEFI_FLAG_INDEX_GUARD)
+    p.exact_idx = r.flags == JEFI_FLAG_INDEX_TABLE || guard_pairs_common(src, obs, ts, g) ? 1 : 0;
   // Longest slice window any brick can need (the 8x8x8 tile bounds both shapes).
   const double wb = std::floor((diam_t + diam_b) * ts.inv_cdt * (1.0 + 1e-12) + 2.0 * p.margin + 1e-6) + 3.0;
   plan->multi = !(wb <= (double)kWmax);
@@ -463,6 +503,7 @@ void drop_graphs(BatchWorkspace& w) {
 }
 
 int slots_per_cu(int wz) { return wz == 2 ? 2 : 4; }
+constexpr int kItemsPerSlot = 12;
 
 jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, hipGraphExec_t* out) {
   hipGraph_t g;
@@ -743,7 +784,8 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
   const int nb = (int)batch_idx.size();
   if (nb == 0) return JEFI_OK;
 
-  // Splits: equal-cost items, at least 4 per workgroup slot.
+  // Splits: equal-cost items, about kItemsPerSlot per workgroup slot, so
+  // that the last items to finish leave little of the device idle.
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -753,7 +795,7 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
     const PairParams& p = cs[batch_idx[k]].plan.p;
     total_cost += (double)p.n_tiles * tile_pts * (double)p.n_bricks * kBrickCells;
   }
-  const double target = std::max(total_cost / (4.0 * cus * slots_per_cu(wz)), 1.0);
+  const double target = std::max(total_cost / ((double)kItemsPerSlot * cus * slots_per_cu(wz)), 1.0);
   std::vector<BatchItem> items;
   std::vector<PairParams> params((size_t)nb);
   std::vector<EpilogueParams> epi((size_t)nb);

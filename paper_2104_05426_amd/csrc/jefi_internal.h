@@ -46,6 +46,8 @@ struct PairParams {
   double near_slack;     // slack on the box screening test, length units
   float guard;           // FP32 index guard half-width, slice units
   int use_thr;           // 1: decide guard-band pairs by the r2 threshold table
+  int exact_idx;         // 1 (needs use_thr): decide every full-brick pair by the table,
+                         // without the FP32 guard test (many pairs near integer positions)
   int thr_lo;            // table covers floor positions thr_lo .. thr_lo + thr_n - 1
   int thr_n;
   double* thr;           // device table of thr_n thresholds (filled by the threshold kernel)

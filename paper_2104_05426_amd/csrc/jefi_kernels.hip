@@ -725,7 +725,9 @@ struct FastShape {
 
 // One workgroup's share of a launch: tile x source split number `bid` of
 // the problem described by p.
-template <typename T, int WZ, bool FP>
+// IDX (FP32 only): 0 = FP32 index with guard band and FP64 re-decision,
+// 1 = threshold-table decision for every pair of a full brick.
+template <typename T, int WZ, bool FP, int IDX>
 __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
                                           float4 (&lds)[FastShape<T, WZ>::NPL * FastShape<T, WZ>::PU],
                                           int4 (&tab_i)[2][FastShape<T, WZ>::G],
@@ -763,6 +765,8 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
   const float af32 = (float)p.a_f, icdt32 = (float)p.inv_cdt, halfg = 0.5f - p.guard;
   const T inv_dt = (T)p.inv_dt;
   const T* ring = (const T*)p.ring;
+  // threshold of floor position N at thr_at[N]; N stays in the table's range
+  const double* thr_at = &thr[0] - p.thr_lo;
   const int b_begin = split * p.bricks_per_split;
   const int b_end = min(b_begin + p.bricks_per_split, p.n_bricks);
 
@@ -814,6 +818,17 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
     __syncthreads();
     load_round(0);
   }
+  // Source-cell index of a brick's first cell (fingerprints only).
+  auto brick_s_base = [&](int b) {
+    const int bz = b / (p.nbx * p.nby);
+    const int by = (b / p.nbx) % p.nby;
+    const int bx = b % p.nbx;
+    return 2 * bx + p.src.n[0] * (2 * by + p.src.n[1] * 2 * bz);
+  };
+  auto cell_s = [&](int s_base, int c) {
+    return s_base + (c & 1) + p.src.n[0] * (((c >> 1) & 1) + p.src.n[1] * (c >> 2));
+  };
+
   for (int rb = b_begin; rb < b_end; rb += G) {
     write_round(buf);
     make_table(rb + G, buf ^ 1);
@@ -821,44 +836,65 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
     if (rb + G < b_end) load_round(buf ^ 1);
 
     float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
-    for (int j = 0; j < G; ++j) {
-      const int4 ti = tab_i[buf][j];
-      if (ti.z & 1) continue;
-      const int lo = ti.x;
-      const int hiw = min(ti.y - lo, kWmax - 1);
-      const int off = p.a_i - lo;  // window slot of slice index m: m + off
-      const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
-      const int mlo = -off, mhi = hiw - off;
-      const double* bc = tab_c[buf][j];
-      int s_base = 0;
-      if (FP) {
-        const int b = ti.w;
-        const int bz = b / (p.nbx * p.nby);
-        const int by = (b / p.nbx) % p.nby;
-        const int bx = b % p.nbx;
-        s_base = 2 * bx + p.src.n[0] * (2 * by + p.src.n[1] * 2 * bz);
-      }
-      const bool fast = (ti.z & 0xff02) == 0xff00;  // all 8 cells present, no screening possible
-      if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4) {
+      // Full far bricks first (all 8 cells, no screening possible), then the
+      // rest (missing cells or possibly screened pairs) in a second pass.
+      unsigned slow = 0;
+#pragma unroll 1
+      for (int j = 0; j < G; ++j) {
+        const int tz = __builtin_amdgcn_readfirstlane(tab_i[buf][j].z);
+        if (tz & 1) continue;
+        if ((tz & 0xff02) != 0xff00) {
+          slow |= 1u << j;
+          continue;
+        }
+        const int4 ti = tab_i[buf][j];
+        const int off = p.a_i - ti.x;  // window slot of floor position m: m + off
+        const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
+        const int mlo = -off;
+        const double* bc = tab_c[buf][j];
         const float4 tf = tab_f[buf][j];
         const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
         const float d1x = d0x - hsx, d1y = d0y - hsy, d1z = d0z - hsz;
-        if (fast) {
-          const float x2[2] = {d0x * d0x, d1x * d1x};
-          const float y2[2] = {d0y * d0y, d1y * d1y};
-          const float z2[2] = {d0z * d0z, d1z * d1z};
-          const float yz[4] = {y2[0] + z2[0], y2[1] + z2[0], y2[0] + z2[1], y2[1] + z2[1]};
-          float ri[8], fr[8];
-          int m[8];
+        const float x2[2] = {d0x * d0x, d1x * d1x};
+        const float y2[2] = {d0y * d0y, d1y * d1y};
+        const float z2[2] = {d0z * d0z, d1z * d1z};
+        const float yz[4] = {y2[0] + z2[0], y2[1] + z2[0], y2[0] + z2[1], y2[1] + z2[1]};
+        float ri[8], fr[8], uu[8];
+        int m[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const float r2 = x2[c & 1] + yz[c >> 1];
+          ri[c] = __builtin_amdgcn_rsqf(r2);
+          uu[c] = __builtin_fmaf(-(r2 * ri[c]), icdt32, af32);
+        }
+        if constexpr (IDX == 1) {
+          // Every pair: N = nearest integer to u32, then floor(u64) = N when
+          // the canonical r2 <= T(N), else N - 1 (|u32 - u64| < 1/2).
+          int nn[8];
+          double tn[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) nn[c] = (int)__builtin_rintf(uu[c]);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) tn[c] = thr_at[nn[c]];
+          const double ex[2] = {rox - bc[0], rox - bc[1]};
+          const double ey[2] = {roy - bc[2], roy - bc[3]};
+          const double ez[2] = {roz - bc[4], roz - bc[5]};
+          const double ez2[2] = {ez[0] * ez[0], ez[1] * ez[1]};
+          const double exy[4] = {ex[0] * ex[0] + ey[0] * ey[0], ex[1] * ex[1] + ey[0] * ey[0],
+                                 ex[0] * ex[0] + ey[1] * ey[1], ex[1] * ex[1] + ey[1] * ey[1]};
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const int mn = exy[c & 3] + ez2[c >> 2] <= tn[c] ? nn[c] : nn[c] - 1;
+            m[c] = mn;
+            fr[c] = uu[c] - (float)mn;
+          }
+        } else {
           bool risky = false;
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
-            const float r2 = x2[c & 1] + yz[c >> 1];
-            ri[c] = __builtin_amdgcn_rsqf(r2);
-            const float R = r2 * ri[c];
-            const float u = __builtin_fmaf(-R, icdt32, af32);
-            const float fl = __builtin_floorf(u);
-            fr[c] = u - fl;
+            const float fl = __builtin_floorf(uu[c]);
+            fr[c] = uu[c] - fl;
             m[c] = (int)fl;
             risky = risky || (__builtin_fabsf(fr[c] - 0.5f) > halfg);
           }
@@ -876,8 +912,7 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
                 if (__builtin_fabsf(fr[c] - 0.5f) > halfg) {
                   const double r2 = exy[c & 3] + ez2[c >> 2];
                   const int N = m[c] + (fr[c] > 0.5f ? 1 : 0);
-                  const int ti_ = min(max(N - p.thr_lo, 0), p.thr_n - 1);
-                  const int mn = r2 <= thr[ti_] ? N : N - 1;
+                  const int mn = r2 <= thr[min(max(N - p.thr_lo, 0), p.thr_n - 1)] ? N : N - 1;
                   fr[c] += (float)(m[c] - mn);
                   m[c] = mn;
                 }
@@ -895,45 +930,78 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
               }
             }
           }
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            if (FP) {
-              const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-              fpa.add(p.a_i + m[c], s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz));
-              continue;
-            }
-            // m <= mhi holds by the window bounds; below mlo lies the zero
-            // entry of pairs wholly before the oldest slice
-            const int e = cellbase + c * kCellStride + max(m[c], mlo);
-            pair_fields(lds, PU, e, fr[c], ri[c], (c & 1) ? d1x : d0x, ((c >> 1) & 1) ? d1y : d0y,
-                        (c >> 2) ? d1z : d0z, bE, bB);
-          }
-        } else {
-          const int vmask = ti.z >> 8;
-          const bool near = (ti.z & 2) != 0;
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            if (!((vmask >> c) & 1)) continue;
-            const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-            if (near && canon_screened(rox - bc[cx], roy - bc[2 + cy], roz - bc[4 + cz], p.screen)) {
-              if (FP) fpa.n_scr += 1;
-              continue;
-            }
-            const float dx = cx ? d1x : d0x, dy = cy ? d1y : d0y, dz = cz ? d1z : d0z;
-            float mf, f, ri;
-            index_f32(dx, dy, dz, af32, icdt32, halfg,
-                      [&]() { return canon_u(rox - bc[cx], roy - bc[2 + cy], roz - bc[4 + cz], p.a_f, p.inv_cdt); },
-                      mf, f, ri);
-            const int mm = (int)mf;
-            if (FP) {
-              fpa.add(p.a_i + mm, s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz));
-              continue;
-            }
-            const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
-            pair_fields(lds, PU, e, f, ri, dx, dy, dz, bE, bB);
-          }
         }
-      } else {
+        if (FP) {
+          const int s_base = brick_s_base(ti.w);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) fpa.add(p.a_i + m[c], cell_s(s_base, c));
+          continue;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          // m <= mhi holds by the window bounds; below mlo lies the zero
+          // entry of pairs wholly before the oldest slice
+          const int e = cellbase + c * kCellStride + max(m[c], mlo);
+          pair_fields(lds, PU, e, fr[c], ri[c], (c & 1) ? d1x : d0x, ((c >> 1) & 1) ? d1y : d0y,
+                      (c >> 2) ? d1z : d0z, bE, bB);
+        }
+      }
+#pragma unroll 1
+      for (int j = 0; slow != 0u; ++j, slow >>= 1) {
+        if (!(slow & 1u)) continue;
+        const int4 ti = tab_i[buf][j];
+        const int lo = ti.x;
+        const int hiw = min(ti.y - lo, kWmax - 1);
+        const int off = p.a_i - lo;
+        const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
+        const int mlo = -off, mhi = hiw - off;
+        const double* bc = tab_c[buf][j];
+        const float4 tf = tab_f[buf][j];
+        const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
+        const float d1x = d0x - hsx, d1y = d0y - hsy, d1z = d0z - hsz;
+        const int s_base = FP ? brick_s_base(ti.w) : 0;
+        const int vmask = ti.z >> 8;
+        const bool near = (ti.z & 2) != 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          if (!((vmask >> c) & 1)) continue;
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          if (near && canon_screened(rox - bc[cx], roy - bc[2 + cy], roz - bc[4 + cz], p.screen)) {
+            if (FP) fpa.n_scr += 1;
+            continue;
+          }
+          const float dx = cx ? d1x : d0x, dy = cy ? d1y : d0y, dz = cz ? d1z : d0z;
+          float mf, f, ri;
+          index_f32(dx, dy, dz, af32, icdt32, halfg,
+                    [&]() { return canon_u(rox - bc[cx], roy - bc[2 + cy], roz - bc[4 + cz], p.a_f, p.inv_cdt); },
+                    mf, f, ri);
+          const int mm = (int)mf;
+          if (FP) {
+            fpa.add(p.a_i + mm, cell_s(s_base, c));
+            continue;
+          }
+          const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
+          pair_fields(lds, PU, e, f, ri, dx, dy, dz, bE, bB);
+        }
+      }
+      if (!FP) {
+        for (int a = 0; a < 3; ++a) {
+          two_sum_acc(sE[a], cE[a], bE[a]);
+          two_sum_acc(sB[a], cB[a], bB[a]);
+        }
+      }
+    } else {
+      for (int j = 0; j < G; ++j) {
+        const int4 ti = tab_i[buf][j];
+        if (ti.z & 1) continue;
+        const int lo = ti.x;
+        const int hiw = min(ti.y - lo, kWmax - 1);
+        const int off = p.a_i - lo;
+        const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
+        const int mlo = -off, mhi = hiw - off;
+        const double* bc = tab_c[buf][j];
+        const int s_base = FP ? brick_s_base(ti.w) : 0;
+        const bool fast = (ti.z & 0xff02) == 0xff00;
         const double dx[2] = {rox - bc[0], rox - bc[1]};
         const double dy[2] = {roy - bc[2], roy - bc[3]};
         const double dz[2] = {roz - bc[4], roz - bc[5]};
@@ -959,19 +1027,11 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
           const double fl = __builtin_floor(u);
           const int mm = (int)__builtin_fmax(fl, -1e9);
           if (FP) {
-            fpa.add(p.a_i + mm, s_base + cx + p.src.n[0] * (cy + p.src.n[1] * cz));
+            fpa.add(p.a_i + mm, cell_s(s_base, c));
             continue;
           }
           const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
           pair_fields(lds, PU, e, u - fl, R, dx[cx], dy[cy], dz[cz], dE, dB);
-        }
-      }
-    }
-    if constexpr (sizeof(T) == 4) {
-      if (!FP) {
-        for (int a = 0; a < 3; ++a) {
-          two_sum_acc(sE[a], cE[a], bE[a]);
-          two_sum_acc(sB[a], cB[a], bB[a]);
         }
       }
     }
@@ -1017,7 +1077,7 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
   }
 }
 
-template <typename T, int WZ, bool FP>
+template <typename T, int WZ, bool FP, int IDX>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
   using S = FastShape<T, WZ>;
   __shared__ float4 lds[S::NPL * S::PU];
@@ -1025,7 +1085,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ float4 tab_f[2][S::G];
   __shared__ double tab_c[2][S::G][6];
   __shared__ double thr[S::THR];
-  pair_body<T, WZ, FP>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr);
+  pair_body<T, WZ, FP, IDX>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr);
 }
 
 // Persistent batched launch: workgroups pull (instance, workgroup id) items
@@ -1049,7 +1109,11 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
     const int2 item = bd.items[it];
     const int inst = __builtin_amdgcn_readfirstlane(item.x);
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
-    pair_body<T, WZ, false>(bd.params[inst], bid, lds, tab_i, tab_f, tab_c, thr);
+    const PairParams& p = bd.params[inst];
+    if (sizeof(T) == 4 && p.exact_idx)
+      pair_body<T, WZ, false, 1>(p, bid, lds, tab_i, tab_f, tab_c, thr);
+    else
+      pair_body<T, WZ, false, 0>(p, bid, lds, tab_i, tab_f, tab_c, thr);
   }
 }
 
@@ -1249,20 +1313,27 @@ hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int mu
   dim3 grid(p.n_wg), block(kThreads);
 #define JEFI_LAUNCH(T, G, FPM, MUL) \
   hipLaunchKernelGGL((pair_kernel<T, G, FPM, MUL>), grid, block, 0, s, p)
-#define JEFI_FAST(T, WZ, FPM) \
-  hipLaunchKernelGGL((pair_kernel_fast<T, WZ, FPM>), grid, dim3(256 * WZ), 0, s, p)
+#define JEFI_FAST(T, WZ, FPM, IDX) \
+  hipLaunchKernelGGL((pair_kernel_fast<T, WZ, FPM, IDX>), grid, dim3(256 * WZ), 0, s, p)
+#define JEFI_FAST_F32(WZ, FPM) \
+  do {                                  \
+    if (p.exact_idx)                    \
+      JEFI_FAST(float, WZ, FPM, 1);     \
+    else                                \
+      JEFI_FAST(float, WZ, FPM, 0);     \
+  } while (0)
   if (!multi_chunk) {
     if (p.tile_z == 8) {
       if (is_f64) {
-        if (fingerprint) JEFI_FAST(double, 2, true); else JEFI_FAST(double, 2, false);
+        if (fingerprint) JEFI_FAST(double, 2, true, 0); else JEFI_FAST(double, 2, false, 0);
       } else {
-        if (fingerprint) JEFI_FAST(float, 2, true); else JEFI_FAST(float, 2, false);
+        if (fingerprint) JEFI_FAST_F32(2, true); else JEFI_FAST_F32(2, false);
       }
     } else {
       if (is_f64) {
-        if (fingerprint) JEFI_FAST(double, 1, true); else JEFI_FAST(double, 1, false);
+        if (fingerprint) JEFI_FAST(double, 1, true, 0); else JEFI_FAST(double, 1, false, 0);
       } else {
-        if (fingerprint) JEFI_FAST(float, 1, true); else JEFI_FAST(float, 1, false);
+        if (fingerprint) JEFI_FAST_F32(1, true); else JEFI_FAST_F32(1, false);
       }
     }
     return hipGetLastError();

@@ -5,7 +5,7 @@ import numpy as np
 PREC = {"f64": (1, 0), "f32": (0, 1)}  # name -> (history dtype, precision)
 
 
-def gpu_eval(p, prec="f32", out_dtype=None, obs=None, capacity=None, screen=None, c=None, tile=0):
+def gpu_eval(p, prec="f32", out_dtype=None, obs=None, capacity=None, screen=None, c=None, tile=0, flags=0):
     import torch
     import paper_2104_05426_amd as J
     hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
@@ -19,6 +19,7 @@ def gpu_eval(p, prec="f32", out_dtype=None, obs=None, capacity=None, screen=None
     opt = J.jefi_options_default(precision=pr, c=c if c is not None else p.c,
                                  screen=screen if screen is not None else p.screen)
     opt.tile_config = tile
+    opt.flags = flags
     J.jefi_eval_fields(p.src, h, p.dt, p.nt, obs, p.t, E[:, :n] if n else E, B[:, :n] if n else B, opt)
     torch.cuda.synchronize()
     out = E[:, :n].double().cpu().numpy(), B[:, :n].double().cpu().numpy()
@@ -26,7 +27,7 @@ def gpu_eval(p, prec="f32", out_dtype=None, obs=None, capacity=None, screen=None
     return out
 
 
-def gpu_fingerprint(p, prec="f32", tile=0):
+def gpu_fingerprint(p, prec="f32", tile=0, flags=0):
     import torch
     import paper_2104_05426_amd as J
     hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
@@ -35,6 +36,7 @@ def gpu_fingerprint(p, prec="f32", tile=0):
     fp = torch.zeros((p.obs.size, 4), dtype=torch.int64, device="cuda")
     opt = J.jefi_options_default(precision=pr, c=p.c, screen=p.screen)
     opt.tile_config = tile
+    opt.flags = flags
     J.jefi_slice_fingerprint(p.src, h, p.dt, p.nt, p.obs, p.t, fp, opt)
     torch.cuda.synchronize()
     out = fp.cpu().numpy()

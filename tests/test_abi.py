@@ -55,7 +55,8 @@ def _grid(n=(4, 4, 4), h=0.1):
 
 @pytest.mark.parametrize("case", [
     "null-src", "bad-spacing", "nt-zero", "nt-over-capacity", "nt-over-pushed", "t-after-newest",
-    "dtype-mismatch", "bad-c", "negative-screen", "null-out", "bad-dt",
+    "dtype-mismatch", "bad-c", "negative-screen", "null-out", "bad-dt", "bad-flags", "both-flags",
+    "bad-tile",
 ])
 def test_eval_validation(case):
     """Each bad input returns EINVAL with a message, before any device call."""
@@ -89,6 +90,12 @@ def test_eval_validation(case):
         fields.E = None
     elif case == "bad-dt":
         dt = 0.0
+    elif case == "bad-flags":
+        opt.flags = 8
+    elif case == "both-flags":
+        opt.flags = J.JEFI_FLAG_INDEX_GUARD | J.JEFI_FLAG_INDEX_TABLE
+    elif case == "bad-tile":
+        opt.tile_config = 3
     st = J.lib.jefi_eval_fields(src_p, C.byref(h), dt, nt, C.byref(obs), t, C.byref(fields),
                                 C.byref(opt), None)
     assert st == J.JEFI_EINVAL

@@ -99,6 +99,22 @@ def test_medium_fields_and_fingerprint(prec, tile):
     assert np.array_equal(fp, fp_ref)
 
 
+@pytest.mark.parametrize("flags", [1, 2])
+@pytest.mark.parametrize("which", ["medium", "ragged"])
+def test_index_modes(which, flags):
+    """Both ways of reaching the canonical slice index in FP32 (guard band
+    with FP64 re-decision; threshold table for every pair) give the oracle's
+    indices bit for bit and its fields within tolerance, on an aligned grid
+    (many exact-integer retarded positions) and a generic one."""
+    G = _gpu()
+    p = _medium() if which == "medium" else _ragged_problem(11)
+    Er, Br = _oracle(p)
+    Eg, Bg = G.gpu_eval(p, "f32", flags=flags)
+    _assert_fields(Eg, Bg, Er, Br, TOL["f32"], f"{which} flags {flags}")
+    fp = G.gpu_fingerprint(p, "f32", flags=flags)
+    assert np.array_equal(fp, _oracle(p, kind="fp"))
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_large_sampled(prec):
     """64^3 x 64^3, 128 slices, at full size in the launch shape the bench
