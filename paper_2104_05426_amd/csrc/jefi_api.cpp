@@ -475,6 +475,9 @@ void attach_history(PairParams& p, const jefi_history* hist, int nt) {
   p.slot_base = (int)((hist->newest - nt + 1) % hist->capacity);
   p.ring = hist->data;
   p.slot_elems = (long long)p.n_bricks * kBrickCells * 4;
+  const unsigned long long rb =
+      (unsigned long long)hist->capacity * (unsigned long long)p.slot_elems * (hist->dtype == JEFI_F64 ? 8ull : 4ull);
+  p.ring_bytes_rs = rb < 0x7ffffff0ull ? (unsigned)rb : 0u;
 }
 
 long long single_target_wg(int tile_z) { return tile_z == 8 ? 8192 : 16384; }
@@ -488,7 +491,7 @@ struct BatchWorkspace {
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_used[2] = {false, false};
   int turn = 0;
-  // graph per (is_f64, wz), valid for the current `dev` buffer
+  // graph per (is_f64, wz, index mode), valid for the current `dev` buffer
   std::map<int, hipGraphExec_t> graphs;
   BatchDevice bd{};
 };
@@ -505,7 +508,7 @@ void drop_graphs(BatchWorkspace& w) {
 int slots_per_cu(int wz) { return wz == 2 ? 2 : 4; }
 constexpr int kItemsPerSlot = 12;
 
-jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, hipGraphExec_t* out) {
+jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, hipGraphExec_t* out) {
   hipGraph_t g;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
@@ -529,7 +532,7 @@ jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, hipGraphExec_t* o
     e = hipGraphAddKernelNode(&n1, g, &n0, 1, &kp);
   }
   if (e == hipSuccess) {
-    kp.func = batch_pair_kernel(is_f64, wz);
+    kp.func = batch_pair_kernel(is_f64, wz, idx);
     kp.gridDim = dim3(cus * slots_per_cu(wz));
     kp.blockDim = dim3(batch_pair_threads(wz));
     e = hipGraphAddKernelNode(&n2, g, &n1, 1, &kp);
@@ -826,6 +829,22 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
     for (int wg = 0; wg < p.n_wg; ++wg) items.push_back({k, wg, item_cost});
   }
   std::stable_sort(items.begin(), items.end(), [](const BatchItem& a, const BatchItem& b) { return a.cost > b.cost; });
+  // One FP32 index mode for the whole launch (both give the same indices):
+  // the threshold table when every instance has one and instances that
+  // prefer it carry at least half of the work.
+  int idx = 0;
+  if (!is_f64) {
+    bool all_thr = true;
+    double want = 0.0, total = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      const PairParams& p = params[k];
+      const double cost = (double)p.n_tiles * tile_pts * (double)p.n_bricks;
+      all_thr = all_thr && p.use_thr;
+      total += cost;
+      if (p.exact_idx) want += cost;
+    }
+    idx = all_thr && 2.0 * want >= total ? 1 : 0;
+  }
   const int n_items = (int)items.size();
 
   // Workspace layout (device): params | items | counts | counter | epi | prefix | thresholds | partials
@@ -927,11 +946,11 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
     drop_graphs(w);
     w.bd = bd;
   }
-  const int gkey = is_f64 * 4 + wz;
+  const int gkey = is_f64 * 8 + idx * 4 + wz;
   auto it = w.graphs.find(gkey);
   if (it == w.graphs.end()) {
     hipGraphExec_t ge;
-    jefi_status st = build_graph(w, is_f64, wz, &ge);
+    jefi_status st = build_graph(w, is_f64, wz, idx, &ge);
     if (st != JEFI_OK) return st;
     it = w.graphs.emplace(gkey, ge).first;
   }

@@ -53,6 +53,7 @@ struct PairParams {
   double* thr;           // device table of thr_n thresholds (filled by the threshold kernel)
   int tile_z;            // observation tile edge in z: 8 (512 threads) or 4 (256 threads)
   const void* ring;      // device ring, library layout
+  unsigned ring_bytes_rs;  // ring bytes when below 2^31 - 16 (buffer-addressed staging), else 0
   long long slot_elems;  // elements (of the ring dtype) per slot
   double* partial;       // FP64 [n_splits][6][n_obs] (unscaled sums)
   void* E;
@@ -104,7 +105,9 @@ hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt,
 // Kernel entry points of a batched evaluation, for graph nodes.
 void* batch_reset_kernel();
 void* batch_threshold_kernel();
-void* batch_pair_kernel(int is_f64, int wz);
+// idx: index mode of the FP32 kernel (1 = threshold table for every pair,
+// needs use_thr in every instance; 0 = guard band).
+void* batch_pair_kernel(int is_f64, int wz, int idx);
 void* batch_epilogue_kernel();
 int batch_pair_threads(int wz);
 hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);

@@ -43,7 +43,8 @@ __device__ __forceinline__ double canon_u(double dx, double dy, double dz, doubl
   return af - R * icdt;
 }
 
-__device__ __forceinline__ bool canon_screened(double dx, double dy, double dz, const double* s) {
+template <class S3>
+__device__ __forceinline__ bool canon_screened(double dx, double dy, double dz, const S3& s) {
   if (__builtin_fabs(dx) <= s[0] && __builtin_fabs(dy) <= s[1] && __builtin_fabs(dz) <= s[2])
     return true;
   double r2 = (dx * dx + dy * dy) + dz * dz;
@@ -81,6 +82,13 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 // Returns floor(u) (clamped below at -1e9) and the weight f.
 // FP32 squared separation, x^2 + (y^2 + z^2) without contraction; the fast
 // pair path forms the same expression from per-brick partial squares.
+// floor(x + 0.5) as an integer in one instruction (|x| well inside int range).
+__device__ __forceinline__ int cvt_nearest(float x) {
+  int n;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(n) : "v"(x));
+  return n;
+}
+
 __device__ __forceinline__ float r2_f32(float dx, float dy, float dz) {
   return dx * dx + (dy * dy + dz * dz);
 }
@@ -125,14 +133,16 @@ __device__ __forceinline__ void two_sum_acc(float& s, float& c, float x) {
 }
 
 // Four channels of one cell at logical slice j (zero outside 0..nt-1).
-__device__ __forceinline__ float4 ring4(const float* ring, const PairParams& p, int j, int b, int c) {
+template <class PP>
+__device__ __forceinline__ float4 ring4(const float* ring, const PP& p, int j, int b, int c) {
   if (j < 0 || j > p.nt - 1) return make_float4(0.f, 0.f, 0.f, 0.f);
   int slot = p.slot_base + j;
   if (slot >= p.capacity) slot -= p.capacity;
   return *(const float4*)(ring + (long long)slot * p.slot_elems + ((long long)b * kBrickCells + c) * 4);
 }
 
-__device__ __forceinline__ void ring4(const double* ring, const PairParams& p, int j, int b, int c,
+template <class PP>
+__device__ __forceinline__ void ring4(const double* ring, const PP& p, int j, int b, int c,
                                       double out[4]) {
   if (j < 0 || j > p.nt - 1) {
     out[0] = out[1] = out[2] = out[3] = 0.0;
@@ -153,7 +163,8 @@ struct TileGeom {
   double refx, refy, refz, thix, thiy, thiz;
 };
 
-__device__ __forceinline__ TileGeom tile_geom(const PairParams& p, int tile) {
+template <class PP>
+__device__ __forceinline__ TileGeom tile_geom(const PP& p, int tile) {
   TileGeom g;
   const int tx = tile % p.ntx;
   const int ty = (tile / p.ntx) % p.nty;
@@ -178,9 +189,12 @@ __device__ __forceinline__ TileGeom tile_geom(const PairParams& p, int tile) {
 // subtraction, squaring, sums and sqrt are monotone, so the bounds hold for
 // the rounded canonical values too).  ti = (wlo, whi, flags, b) with flags
 // bit0 = dead (whole window before the oldest slice), bit1 = near (some pair
-// may be screened), bits 8..15 = valid cells; tf = brick corner relative to
+// may be screened), bit2 = some pair lies before slot -2 (its floor position
+// must be clamped to the window's zero entry), bits 8..15 = valid cells;
+// tf = brick corner relative to
 // the tile reference in FP32; cc = canonical x0, x1, y0, y1, z0, z1.
-__device__ __forceinline__ void brick_info(const PairParams& p, const TileGeom& g, int b, int b_end,
+template <class PP>
+__device__ __forceinline__ void brick_info(const PP& p, const TileGeom& g, int b, int b_end,
                                            int4& ti, float4& tf, double cc[6]) {
   ti = make_int4(0, -1, 1, b);
   tf = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -212,18 +226,18 @@ __device__ __forceinline__ void brick_info(const PairParams& p, const TileGeom& 
     f2 += far * far;
     near = near && (gap <= p.screen[a] + p.near_slack);
   }
+  // correctly rounded square roots: the bounds then hold for the rounded
+  // canonical values by monotonicity (the hardware v_sqrt_f64 alone is far
+  // less accurate than the margin)
   const double ulo = p.a_f - __builtin_sqrt(f2) * p.inv_cdt - p.margin;
   const double uhi = p.a_f - __builtin_sqrt(g2) * p.inv_cdt + p.margin;
   const int jlo = p.a_i + (int)__builtin_fmax(__builtin_floor(ulo), -1e9);
   int jhi = p.a_i + (int)__builtin_fmax(__builtin_floor(uhi), -1e9);
   jhi = min(jhi, p.nt - 1);
   const bool dead = jhi < -1;
-  int vmask = 0;
-  for (int c = 0; c < 8; ++c) {
-    const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-    if (i0 + cx <= i1 && j0 + cy <= j1 && k0 + cz <= k1) vmask |= 1 << c;
-  }
-  ti = make_int4(max(jlo, -2), jhi, (dead ? 1 : 0) | (near ? 2 : 0) | (vmask << 8), b);
+  // cells with cx = 1 (cy = 1, cz = 1) exist when the brick has two layers in x (y, z)
+  const int vmask = (i1 > i0 ? 0xff : 0x55) & (j1 > j0 ? 0xff : 0x33) & (k1 > k0 ? 0xff : 0x0f);
+  ti = make_int4(max(jlo, -2), jhi, (dead ? 1 : 0) | (near ? 2 : 0) | (jlo < -2 ? 4 : 0) | (vmask << 8), b);
   tf = make_float4((float)(cc[0] - g.refx), (float)(cc[2] - g.refy), (float)(cc[4] - g.refz), 0.f);
 }
 
@@ -563,16 +577,36 @@ struct D4 {
   double x, y, z, w;
 };
 
-__device__ __forceinline__ void load_raw(const float* ring, const PairParams& p, int jj, int b, int c,
+template <class PP>
+__device__ __forceinline__ void load_raw(const float* ring, const PP& p, int jj, int b, int c,
                                          float4& out) {
   out = ring4(ring, p, jj, b, c);
 }
 
-__device__ __forceinline__ void load_raw(const double* ring, const PairParams& p, int jj, int b, int c,
+template <class PP>
+__device__ __forceinline__ void load_raw(const double* ring, const PP& p, int jj, int b, int c,
                                          D4& out) {
   double v[4];
   ring4(ring, p, jj, b, c, v);
   out = D4{v[0], v[1], v[2], v[3]};
+}
+
+// Raw buffer resource word 3 for gfx9-family targets (32-bit data, no
+// swizzle); offsets at or beyond the resource's byte count read as zero.
+constexpr int kRawBufferFlags = 0x00020000;
+constexpr int kOutOfRange = 0x7ffffff0;  // above any ring the buffer path takes
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, int off, float4& out) {
+  const f32x4_t v = __builtin_bit_cast(f32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  out = make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, int off, D4& out) {
+  const f64x2_t lo = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  const f64x2_t hi = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 16, 0));
+  out = D4{lo.x, lo.y, hi.x, hi.y};
 }
 
 __device__ __forceinline__ void zero_raw(float4& v) { v = make_float4(0.f, 0.f, 0.f, 0.f); }
@@ -726,9 +760,11 @@ struct FastShape {
 // One workgroup's share of a launch: tile x source split number `bid` of
 // the problem described by p.
 // IDX (FP32 only): 0 = FP32 index with guard band and FP64 re-decision,
-// 1 = threshold-table decision for every pair of a full brick.
-template <typename T, int WZ, bool FP, int IDX>
-__device__ __forceinline__ void pair_body(const PairParams& p, int bid,
+// 1 = threshold-table decision for every pair of a full brick.  PP is
+// PairParams as a kernel argument, or in the constant address space for
+// the persistent kernel (uniform, read-only: scalar loads).
+template <typename T, int WZ, bool FP, int IDX, class PP>
+__device__ __forceinline__ void pair_body(const PP& p, int bid,
                                           float4 (&lds)[FastShape<T, WZ>::NPL * FastShape<T, WZ>::PU],
                                           int4 (&tab_i)[2][FastShape<T, WZ>::G],
                                           float4 (&tab_f)[2][FastShape<T, WZ>::G],
@@ -795,6 +831,29 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
   auto load_round = [&](int buf) {
     const int4 ti = tab_i[buf][sj];
     const int k0 = ti.x + sq * EPT;
+    if (p.ring_bytes_rs != 0u) {
+      // Buffer addressing over the ring: 32-bit offsets stepped slot by
+      // slot, and slices outside 0..nt-1 read through an offset past the
+      // end of the buffer, which the hardware returns as zero.
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)p.ring, (short)0, (int)p.ring_bytes_rs, kRawBufferFlags);
+      const unsigned sb = (unsigned)p.slot_elems * (unsigned)sizeof(T);
+      const int j0 = (ti.z & 1) ? p.nt : k0 - 1;  // dead bricks: every load out of range
+      int sl = p.slot_base + j0;  // j0 >= -3
+      sl += sl < 0 ? p.capacity : 0;
+      sl += sl < 0 ? p.capacity : 0;
+      sl += sl < 0 ? p.capacity : 0;
+      sl -= sl >= p.capacity ? p.capacity : 0;
+      unsigned off = (unsigned)sl * sb + ((unsigned)ti.w * kBrickCells + (unsigned)sc) * (4u * (unsigned)sizeof(T));
+#pragma unroll
+      for (int r = 0; r < NRAW; ++r) {
+        const int o = (unsigned)(j0 + r) < (unsigned)p.nt ? (int)off : kOutOfRange;
+        buffer_raw(rs, o, raw[r]);
+        off += sb;
+        off -= off >= p.ring_bytes_rs ? p.ring_bytes_rs : 0u;
+      }
+      return;
+    }
 #pragma unroll
     for (int r = 0; r < NRAW; ++r) {
       if (ti.z & 1)
@@ -874,7 +933,7 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
           int nn[8];
           double tn[8];
 #pragma unroll
-          for (int c = 0; c < 8; ++c) nn[c] = (int)__builtin_rintf(uu[c]);
+          for (int c = 0; c < 8; ++c) nn[c] = cvt_nearest(uu[c]);
 #pragma unroll
           for (int c = 0; c < 8; ++c) tn[c] = thr_at[nn[c]];
           const double ex[2] = {rox - bc[0], rox - bc[1]};
@@ -937,13 +996,19 @@ __device__ __forceinline__ void pair_body(const PairParams& p, int bid,
           for (int c = 0; c < 8; ++c) fpa.add(p.a_i + m[c], cell_s(s_base, c));
           continue;
         }
+        // m <= mhi holds by the window bounds; below mlo lies the zero
+        // entry of pairs wholly before the oldest slice, which only bricks
+        // flagged by bit 2 can have
+        if (tz & 4) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          // m <= mhi holds by the window bounds; below mlo lies the zero
-          // entry of pairs wholly before the oldest slice
-          const int e = cellbase + c * kCellStride + max(m[c], mlo);
-          pair_fields(lds, PU, e, fr[c], ri[c], (c & 1) ? d1x : d0x, ((c >> 1) & 1) ? d1y : d0y,
-                      (c >> 2) ? d1z : d0z, bE, bB);
+          for (int c = 0; c < 8; ++c)
+            pair_fields(lds, PU, cellbase + c * kCellStride + max(m[c], mlo), fr[c], ri[c], (c & 1) ? d1x : d0x,
+                        ((c >> 1) & 1) ? d1y : d0y, (c >> 2) ? d1z : d0z, bE, bB);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            pair_fields(lds, PU, cellbase + c * kCellStride + m[c], fr[c], ri[c], (c & 1) ? d1x : d0x,
+                        ((c >> 1) & 1) ? d1y : d0y, (c >> 2) ? d1z : d0z, bE, bB);
         }
       }
 #pragma unroll 1
@@ -1089,8 +1154,9 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
 }
 
 // Persistent batched launch: workgroups pull (instance, workgroup id) items
-// from a queue ordered heaviest first until it is empty.
-template <typename T, int WZ>
+// from a queue ordered heaviest first until it is empty.  IDX as for
+// pair_body, one value for the whole batch.
+template <typename T, int WZ, int IDX>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_persistent(BatchDevice bd) {
   using S = FastShape<T, WZ>;
   __shared__ float4 lds[S::NPL * S::PU];
@@ -1109,11 +1175,9 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
     const int2 item = bd.items[it];
     const int inst = __builtin_amdgcn_readfirstlane(item.x);
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
-    const PairParams& p = bd.params[inst];
-    if (sizeof(T) == 4 && p.exact_idx)
-      pair_body<T, WZ, false, 1>(p, bid, lds, tab_i, tab_f, tab_c, thr);
-    else
-      pair_body<T, WZ, false, 0>(p, bid, lds, tab_i, tab_f, tab_c, thr);
+    using CP = const __attribute__((address_space(4))) PairParams;
+    CP& p = *(CP*)(bd.params + inst);
+    pair_body<T, WZ, false, IDX>(p, bid, lds, tab_i, tab_f, tab_c, thr);
   }
 }
 
@@ -1365,9 +1429,12 @@ hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt,
 void* batch_reset_kernel() { return (void*)batch_reset; }
 void* batch_threshold_kernel() { return (void*)batch_threshold; }
 void* batch_epilogue_kernel() { return (void*)batch_epilogue; }
-void* batch_pair_kernel(int is_f64, int wz) {
-  if (is_f64) return wz == 2 ? (void*)pair_kernel_persistent<double, 2> : (void*)pair_kernel_persistent<double, 1>;
-  return wz == 2 ? (void*)pair_kernel_persistent<float, 2> : (void*)pair_kernel_persistent<float, 1>;
+void* batch_pair_kernel(int is_f64, int wz, int idx) {
+  if (is_f64)
+    return wz == 2 ? (void*)pair_kernel_persistent<double, 2, 0> : (void*)pair_kernel_persistent<double, 1, 0>;
+  if (idx)
+    return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 1> : (void*)pair_kernel_persistent<float, 1, 1>;
+  return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 0> : (void*)pair_kernel_persistent<float, 1, 0>;
 }
 int batch_pair_threads(int wz) { return 256 * wz; }
 

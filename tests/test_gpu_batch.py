@@ -72,6 +72,18 @@ def test_batch_equals_solo_and_oracle(prec, tile):
     print(f"batch of {len(probs)} ({prec}, tile {tile}) matches solo and oracle", flush=True)
 
 
+@pytest.mark.parametrize("flags", [1, 2])
+def test_batch_index_modes(flags):
+    """The persistent kernel in both FP32 index modes (guard band; threshold
+    table for every pair) matches the single launches in the same mode."""
+    G = _gpu()
+    probs = _small_batch(10, seed=17)
+    run = G.BatchRun(probs, "f32")
+    solo = run.run_solo(1, flags)
+    batch = run.run_batch(1, flags)
+    _check_against(batch, solo, SOLO["f32"], f"batch vs solo flags {flags}")
+
+
 def test_graph_replays_agree():
     """Several replays of the captured launch sequence, with eager work and
     synchronisations in between, each equal to the first."""
