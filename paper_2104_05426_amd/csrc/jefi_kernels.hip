@@ -1000,6 +1000,12 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         // entry of pairs wholly before the oldest slice, which only bricks
         // flagged by bit 2 can have
         if (tz & 4) {
+          // a brick straddling the switch-on front: skip it for this wavefront
+          // when every pair lies before slice -1 (all contributions are zero)
+          int mmax = m[0];
+#pragma unroll
+          for (int c = 1; c < 8; ++c) mmax = max(mmax, m[c]);
+          if (!__any(mmax >= -1 - p.a_i)) continue;
 #pragma unroll
           for (int c = 0; c < 8; ++c)
             pair_fields(lds, PU, cellbase + c * kCellStride + max(m[c], mlo), fr[c], ri[c], (c & 1) ? d1x : d0x,
