@@ -465,7 +465,7 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                      "traffic": profiled_traffic(args.workload),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "kernel": "pair_kernel<float> (+ epilogue) per jefi_eval_fields, HIP events",
+                     "kernel": "pair_kernel_fast<float> (+ epilogue) per jefi_eval_fields, HIP events on its stream",
                      "flops_per_live_pair": FLOPS_PER_LIVE_PAIR},
     }
 
