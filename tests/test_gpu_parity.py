@@ -303,6 +303,44 @@ def test_ring_wraparound_matches_fresh_upload():
     assert np.array_equal(Eg2, E.double().cpu().numpy()) and np.array_equal(Bg2, B.double().cpu().numpy())
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_ring_above_2gib_matches_small_ring(prec):
+    """A ring of more than 2 GiB (64-bit staging addresses) gives exactly
+    the fields of a ring holding only the used steps (32-bit buffer
+    addressing), and the oracle's on sampled points."""
+    import torch
+    import paper_2104_05426_amd as J
+    G = _gpu()
+    src = centred_grid((64, 64, 64), 0.025)
+    obs = Grid((8, 8, 8), tuple(src.origin[a] + (28 + (8 if a == 0 else 0)) * 0.025 for a in range(3)),
+               (0.025, 0.025, 0.025))
+    dt, total, nt = 0.0125, 14, 12
+    blobs = workloads.draw_blobs(np.random.default_rng(21), 6, (-0.8, 0.8))
+    hall = blob_history(src, blobs, total, dt)
+    hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
+    cap = 600 if prec == "f32" else 300
+    assert J.jefi_history_bytes(src, cap, hdt) > (1 << 31)
+    t = (total - 1) * dt
+    outs = []
+    for capacity in (cap, nt):
+        store, h = J.upload_history(src, hall[total - nt:], hdt, newest=total - 1, capacity=capacity)
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        E = torch.empty((3, obs.size), dtype=tdt, device="cuda")
+        B = torch.empty((3, obs.size), dtype=tdt, device="cuda")
+        opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP)
+        J.jefi_eval_fields(src, h, dt, nt, obs, t, E, B, opt)
+        torch.cuda.synchronize()
+        outs.append((E.double().cpu().numpy(), B.double().cpu().numpy()))
+        del store
+        torch.cuda.empty_cache()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    rng = np.random.default_rng(5)
+    sel = np.sort(rng.choice(obs.size, size=24, replace=False))
+    p = Problem("big-ring", src, obs, hall[total - nt:], dt, t, 0.0, total - 1, 1.0, workloads.default_screen(src))
+    Er, Br = oracle.eval_problem(p, sel=sel)
+    _assert_fields(outs[0][0][:, sel], outs[0][1][:, sel], Er, Br, TOL[prec], f"ring > 2 GiB {prec}")
+
+
 def test_deterministic_repeat():
     G = _gpu()
     p = _medium()

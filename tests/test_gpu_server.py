@@ -15,8 +15,8 @@ from workloads import Grid, Problem, blob_history, centred_grid
 
 pytestmark = pytest.mark.gpu
 
-SOLO_TOL = 2e-6   # FP32 batched vs FP32 alone (different split sums)
-ORACLE_TOL = 1e-5
+SOLO_TOL = {"f32": 2e-6, "f64": 1e-13}    # batched vs alone (different split sums)
+ORACLE_TOL = {"f32": 1e-5, "f64": 1e-12}
 
 
 def _gpu():
@@ -48,29 +48,34 @@ def _obs_for(sess, rng):
     return Grid((eo, eo, eo), tuple(sess["src"].origin[a] + m * dx for a in range(3)), (dx, dx, dx))
 
 
-def _solo(J, src, hist_window, dt, newest, obs, t):
+def _solo(J, src, hist_window, dt, newest, obs, t, prec="f32"):
     """One evaluation alone: a ring holding exactly the window."""
     import torch
-    store, h = J.upload_history(src, hist_window, J.JEFI_F32, t0=0.0, newest=newest)
-    E = torch.empty((3, max(obs.size, 1)), dtype=torch.float32, device="cuda")
+    f64 = prec == "f64"
+    store, h = J.upload_history(src, hist_window, J.JEFI_F64 if f64 else J.JEFI_F32, t0=0.0, newest=newest)
+    E = torch.empty((3, max(obs.size, 1)), dtype=torch.float64 if f64 else torch.float32, device="cuda")
     B = torch.empty_like(E)
-    J.jefi_eval_fields(src, h, dt, hist_window.shape[0], obs, t, E[:, :obs.size], B[:, :obs.size])
+    opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if f64 else J.JEFI_PREC_F32_COMP)
+    J.jefi_eval_fields(src, h, dt, hist_window.shape[0], obs, t, E[:, :obs.size], B[:, :obs.size], opt)
     torch.cuda.synchronize()
     return E[:, :obs.size].double().cpu().numpy(), B[:, :obs.size].double().cpu().numpy()
 
 
-def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6):
+def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32"):
     import torch
     rng = np.random.default_rng(seed)
     sess = _sessions(n_sessions, seed)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
-    sv = J.Server(arena, precision=J.JEFI_PREC_F32_COMP, max_inflight=2, max_batch=64)
+    f64 = prec == "f64"
+    ndt = np.float64 if f64 else np.float32
+    sv = J.Server(arena, precision=J.JEFI_PREC_F64 if f64 else J.JEFI_PREC_F32_COMP, max_inflight=2,
+                  max_batch=64)
     full = {}
     for s in sess:
         steps = init_steps + n_req  # enough slices for every push
         full[s["id"]] = blob_history(s["src"], s["blobs"], steps, s["dt"])
         sv.open_session(s["id"], s["src"], s["cap"], s["window"], 0.0, s["dt"],
-                        full[s["id"]][:init_steps].astype(np.float32))
+                        full[s["id"]][:init_steps].astype(ndt))
     newest = {s["id"]: init_steps - 1 for s in sess}
     reqs = []
     for q in range(n_req):
@@ -78,9 +83,9 @@ def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6):
         sid = s["id"]
         newest[sid] += 1
         obs = _obs_for(s, rng)
-        E = np.full((3, obs.size), np.nan, dtype=np.float32)
-        B = np.full((3, obs.size), np.nan, dtype=np.float32)
-        st, tk = sv.submit(sid, obs, E, B, new_slice=full[sid][newest[sid]].astype(np.float32))
+        E = np.full((3, obs.size), np.nan, dtype=ndt)
+        B = np.full((3, obs.size), np.nan, dtype=ndt)
+        st, tk = sv.submit(sid, obs, E, B, new_slice=full[sid][newest[sid]].astype(ndt))
         assert st == J.JEFI_OK, J.jefi_last_error()
         reqs.append(dict(ticket=tk, sid=sid, newest=newest[sid], obs=obs, E=E, B=B, s=s))
     results = []
@@ -93,24 +98,26 @@ def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6):
     return reqs, results, stats, full
 
 
-def _check_solo(J, reqs, full, n_oracle=4):
+def _check_solo(J, reqs, full, n_oracle=4, prec="f32"):
     rng = np.random.default_rng(1)
     for i, r in enumerate(reqs):
         s = r["s"]
         nt = min(s["window"], r["newest"] + 1)
-        window = full[r["sid"]][r["newest"] - nt + 1:r["newest"] + 1].astype(np.float32).astype(np.float64)
+        window = full[r["sid"]][r["newest"] - nt + 1:r["newest"] + 1]
+        if prec == "f32":
+            window = window.astype(np.float32).astype(np.float64)
         t = r["newest"] * s["dt"]
-        Es, Bs = _solo(J, s["src"], window, s["dt"], r["newest"], r["obs"], t)
+        Es, Bs = _solo(J, s["src"], window, s["dt"], r["newest"], r["obs"], t, prec)
         e, _ = rel_l2(r["E"].astype(np.float64), Es)
         b, _ = rel_l2(r["B"].astype(np.float64), Bs)
-        assert max(e + b) <= SOLO_TOL, (i, e, b)
+        assert max(e + b) <= SOLO_TOL[prec], (i, e, b)
         if i < n_oracle:
             p = Problem("srv", s["src"], r["obs"], window, s["dt"], t, 0.0, r["newest"], 1.0,
                         workloads.default_screen(s["src"]))
             Er, Br = oracle.eval_problem(p)
             e, _ = rel_l2(r["E"].astype(np.float64), Er)
             b, _ = rel_l2(r["B"].astype(np.float64), Br)
-            assert max(e + b) <= ORACLE_TOL, (i, e, b)
+            assert max(e + b) <= ORACLE_TOL[prec], (i, e, b)
 
 
 def test_server_results_equal_solo_in_the_mix():
@@ -124,6 +131,15 @@ def test_server_results_equal_solo_in_the_mix():
     for r in results:
         assert r.t_submit_ns <= r.t_admit_ns <= r.t_start_ns <= r.t_done_ns
     _check_solo(J, reqs, full)
+
+
+def test_server_fp64_results_equal_solo():
+    """The server in FP64: FP64 rings, FP64 outputs, each result equal to
+    the same FP64 evaluation alone and to the oracle."""
+    J = _gpu()
+    reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=4, n_req=24, seed=8, prec="f64")
+    assert stats["completed"] == 24 and stats["failed"] == 0
+    _check_solo(J, reqs, full, n_oracle=3, prec="f64")
 
 
 def test_server_evicts_and_rematerialises():
