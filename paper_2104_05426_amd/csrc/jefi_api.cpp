@@ -346,6 +346,10 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
     }
   }
   p.guard = (float)g;
+  // A brick counts as far (fast path, no per-pair screening test) only when
+  // its box is farther than the screening width plus more than the FP32
+  // coordinate error on some axis: every FP32 separation there is nonzero.
+  p.near_slack = std::max(1e-12, 4.0 * e_coord);
   p.exact_idx = 0;
   if (p.use_thr && r.flags != JEFI_FLAG_INDEX_GUARD)
     p.exact_idx = r.flags == JEFI_FLAG_INDEX_TABLE || guard_pairs_common(src, obs, ts, g) ? 1 : 0;

@@ -103,7 +103,8 @@ __device__ __forceinline__ void index_f32(float dx, float dy, float dz, float af
   float u = __builtin_fmaf(-R, icdt, af);
   float fl = __builtin_floorf(u);
   float fr = u - fl;
-  if (__builtin_expect(__builtin_fabsf(fr - 0.5f) > halfg, 0)) {
+  // NaN (a separation below FP32 resolution) also takes the FP64 decision
+  if (__builtin_expect(!(__builtin_fabsf(fr - 0.5f) <= halfg), 0)) {
     double u64 = canon_fn();
     double m64 = __builtin_floor(u64);
     fl = (float)__builtin_fmax(m64, -1e9);
@@ -955,7 +956,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
             const float fl = __builtin_floorf(uu[c]);
             fr[c] = uu[c] - fl;
             m[c] = (int)fl;
-            risky = risky || (__builtin_fabsf(fr[c] - 0.5f) > halfg);
+            risky = risky || !(__builtin_fabsf(fr[c] - 0.5f) <= halfg);
           }
           if (risky) {
             if (p.use_thr) {
@@ -968,7 +969,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
                                      ex[0] * ex[0] + ey[1] * ey[1], ex[1] * ex[1] + ey[1] * ey[1]};
 #pragma unroll
               for (int c = 0; c < 8; ++c) {
-                if (__builtin_fabsf(fr[c] - 0.5f) > halfg) {
+                if (!(__builtin_fabsf(fr[c] - 0.5f) <= halfg)) {
                   const double r2 = exy[c & 3] + ez2[c >> 2];
                   const int N = m[c] + (fr[c] > 0.5f ? 1 : 0);
                   const int mn = r2 <= thr[min(max(N - p.thr_lo, 0), p.thr_n - 1)] ? N : N - 1;
@@ -979,7 +980,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
             } else {
 #pragma unroll
               for (int c = 0; c < 8; ++c) {
-                if (__builtin_fabsf(fr[c] - 0.5f) > halfg) {
+                if (!(__builtin_fabsf(fr[c] - 0.5f) <= halfg)) {
                   const double u64 = canon_u(rox - bc[c & 1], roy - bc[2 + ((c >> 1) & 1)],
                                              roz - bc[4 + (c >> 2)], p.a_f, p.inv_cdt);
                   const double m64 = __builtin_floor(u64);

@@ -99,6 +99,17 @@ def test_medium_fields_and_fingerprint(prec, tile):
     assert np.array_equal(fp, fp_ref)
 
 
+def test_tile_shapes_agree():
+    """The two launch shapes sum in different orders; their results agree
+    far inside the tolerance (FP32 1e-6, FP64 1e-14)."""
+    G = _gpu()
+    p = _medium()
+    for prec, tol in (("f32", 1e-6), ("f64", 1e-14)):
+        E1, B1 = G.gpu_eval(p, prec, tile=1)
+        E2, B2 = G.gpu_eval(p, prec, tile=2)
+        _assert_fields(E1, B1, E2, B2, tol, f"tile shapes {prec}")
+
+
 @pytest.mark.parametrize("flags", [1, 2])
 @pytest.mark.parametrize("which", ["medium", "ragged"])
 def test_index_modes(which, flags):
@@ -227,6 +238,39 @@ def test_random_pairs_dump_bit_exact():
         ref = oracle.slice_index_dump(src, obs, nt, dt, t, 0.0, newest, 1.0, (0.0, 0.0, 0.0))
         for prec in ["f64", "f32"]:
             assert np.array_equal(G.gpu_dump(p, prec), ref)
+
+
+@pytest.mark.parametrize("kind", ["random", "aligned"])
+def test_index_function_on_1e7_pairs(kind):
+    """About 10^7 pairs, per-pair slice indices from the dump kernel and
+    per-point fingerprints from the field kernel in both FP32 index modes,
+    all equal to the oracle's canonical FP64 decisions.  'aligned' puts a
+    few percent of the pairs at exact integer retarded positions."""
+    G = _gpu()
+    rng = np.random.default_rng(99 if kind == "random" else 98)
+    if kind == "random":
+        src = Grid((31, 29, 23), tuple(rng.uniform(-1, 0, 3)), tuple(rng.uniform(0.01, 0.04, 3)))
+        obs = Grid((10, 10, 5), tuple(rng.uniform(-0.5, 1.5, 3)), tuple(rng.uniform(0.01, 0.08, 3)))
+        dt = float(rng.uniform(0.002, 0.01))
+    else:
+        h = 0.02
+        src = centred_grid((31, 29, 23), h)
+        obs = src.shifted_cells(9, -4, 3)
+        obs = Grid((10, 10, 5), obs.origin, obs.spacing)
+        dt = h / 2.0  # c*dt divides the spacing
+    nt = 400
+    newest = nt - 1 + int(rng.integers(0, 10 ** 5))
+    t = newest * dt
+    screen = (0.0, 0.0, 0.0)
+    p = Problem(kind, src, obs, np.zeros((nt, 4, src.size)), dt, t, 0.0, newest, 1.0, screen)
+    assert src.size * obs.size > 10 ** 7
+    ref = oracle.slice_index_dump(src, obs, nt, dt, t, 0.0, newest, 1.0, screen)
+    for prec in ["f64", "f32"]:
+        assert np.array_equal(G.gpu_dump(p, prec), ref), prec
+    fp_ref = _oracle(p, kind="fp")
+    assert np.array_equal(G.gpu_fingerprint(p, "f64"), fp_ref)
+    for flags in (1, 2):
+        assert np.array_equal(G.gpu_fingerprint(p, "f32", flags=flags), fp_ref), flags
 
 
 def test_edge_cases():
