@@ -247,9 +247,11 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
 
 /* A session: source grid, ring capacity, evaluation window (slices used,
  * 1 <= window <= capacity), time axis (step s at t0 + s*dt), and optionally
- * its first init_nt steps (HOST [init_nt][4][n_src], oldest first).
- * EINVAL for a used id or bad sizes; ETOOLARGE when the ring can never fit
- * the arena. */
+ * its first init_nt steps (HOST [init_nt][4][n_src], oldest first; copied
+ * before return).  The ring is uploaded into the arena before return when
+ * there is room (idle sessions may be evicted for it), else when its first
+ * request is admitted.  EINVAL for a used id or bad sizes; ETOOLARGE when
+ * the ring can never fit the arena; EDEVICE on a HIP failure. */
 jefi_status jefi_server_open_session(jefi_server* sv, uint64_t session, const jefi_grid* src, int32_t capacity,
                                      int32_t window, double t0, double dt, const void* init_history,
                                      int32_t init_nt);

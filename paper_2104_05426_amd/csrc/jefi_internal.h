@@ -99,6 +99,10 @@ struct DumpParams {
 hipError_t launch_zero(void* p, unsigned long long bytes, hipStream_t s);
 hipError_t launch_ingest(const void* slice, void* slot, const GridD& src, int nbx, int nby,
                          int is_f64, hipStream_t s);
+// All n_slots slots of a history in host layout [n_slots][4][n_src] (device
+// memory) into the first n_slots ring slots.
+hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, int nbx, int nby, int n_slots,
+                               int is_f64, hipStream_t s);
 hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk,
                         hipStream_t s);
 hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt, hipStream_t s);

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "jefi_internal.h"
 
 namespace jefi {
@@ -1277,6 +1279,28 @@ __global__ void ingest_kernel(const T* slice, T* slot, GridD src, int nbx, int n
   }
 }
 
+// Every slot of a host-layout history [n_slots][4][n] into ring slots of the
+// brick layout (blockIdx.y = slot).
+template <typename T>
+__global__ void ingest_slots_kernel(const T* hist, T* ring, GridD src, int nbx, int nby, long long slot_elems) {
+  const long long n = (long long)src.n[0] * src.n[1] * src.n[2];
+  const T* slice = hist + (long long)blockIdx.y * 4 * n;
+  T* slot = ring + (long long)blockIdx.y * slot_elems;
+  for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n;
+       s += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(s % src.n[0]);
+    const int j = (int)((s / src.n[0]) % src.n[1]);
+    const int k = (int)(s / ((long long)src.n[0] * src.n[1]));
+    const long long b = (long long)(i >> 1) + (long long)nbx * ((j >> 1) + (long long)nby * (k >> 1));
+    const int c = (i & 1) + 2 * (j & 1) + 4 * (k & 1);
+    T* dst = slot + (b * kBrickCells + c) * 4;
+    dst[0] = slice[s];
+    dst[1] = slice[n + s];
+    dst[2] = slice[2 * n + s];
+    dst[3] = slice[3 * n + s];
+  }
+}
+
 __global__ void fill_zero_fields(void* E, void* B, long long n, int f64) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -1377,6 +1401,30 @@ hipError_t launch_ingest(const void* slice, void* slot, const GridD& src, int nb
     hipLaunchKernelGGL(ingest_kernel<float>, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        (const float*)slice, (float*)slot, src, nbx, nby);
   return hipGetLastError();
+}
+
+hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, int nbx, int nby, int n_slots,
+                               int is_f64, hipStream_t s) {
+  const long long n = (long long)src.n[0] * src.n[1] * src.n[2];
+  if (n == 0 || n_slots <= 0) return hipSuccess;
+  const long long nb = (long long)nbx * nby * (((long long)src.n[2] + 1) / 2);
+  const long long slot_elems = nb * kBrickCells * 4;
+  const size_t esz = is_f64 ? 8 : 4;
+  for (int first = 0; first < n_slots; first += 65535) {
+    const int cnt = std::min(65535, n_slots - first);
+    const dim3 grid((unsigned)std::min<long long>(grid_for(n, 256), 1024), (unsigned)cnt);
+    const char* h = (const char*)hist + (size_t)first * 4 * (size_t)n * esz;
+    char* r = (char*)ring + (size_t)first * (size_t)slot_elems * esz;
+    if (is_f64)
+      hipLaunchKernelGGL(ingest_slots_kernel<double>, grid, dim3(256), 0, s, (const double*)h, (double*)r, src,
+                         nbx, nby, slot_elems);
+    else
+      hipLaunchKernelGGL(ingest_slots_kernel<float>, grid, dim3(256), 0, s, (const float*)h, (float*)r, src, nbx,
+                         nby, slot_elems);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk,

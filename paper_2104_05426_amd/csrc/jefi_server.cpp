@@ -56,6 +56,7 @@ struct Session {
   bool evicted = false;  // left the arena at least once since it was opened
   uint64_t ring_off = 0, ring_bytes = 0;
   int busy = 0;      // requests admitted and not finished
+  hipEvent_t last_done = nullptr;  // completion event of the batch holding its latest admitted request
   int queued = 0;    // requests submitted and not admitted
   uint64_t last_use = 0;
 };
@@ -109,7 +110,7 @@ struct jefi_server {
   std::unordered_map<uint64_t, Req> reqs;
   std::unordered_map<uint64_t, Session> sessions;
   std::deque<Batch> inflight;
-  int next_stream = 0;
+  hipStream_t setup = nullptr;  // eager ring uploads at open_session
   std::thread th;
   bool stop = false;
   uint64_t next_ticket = 1, use_clock = 0;
@@ -152,52 +153,51 @@ bool make_room(jefi_server* sv, uint64_t bytes, const std::unordered_set<uint64_
   return true;
 }
 
-// Bring a session's ring onto the device from its host shadow: one upload
-// of the shadow into a staging region, then one ingest per stored step.
-jefi_status materialise(jefi_server* sv, Session& s, hipStream_t st, Batch& b,
-                        const std::unordered_set<uint64_t>& keep) {
+// Bring a session's ring onto the device: the whole host shadow (every
+// slot, zeros where nothing was pushed) goes to a device staging region and
+// one kernel lays every slot out into the ring.  The copy reads pageable host
+// memory, so the shadow may change as soon as this returns; the staging
+// region (returned in *staging) must outlive the kernel, i.e. be released
+// only after `st` has passed this point.
+jefi_status materialise(jefi_server* sv, Session& s, hipStream_t st, const std::unordered_set<uint64_t>& keep,
+                        Region* staging) {
+  staging->device = true;
+  staging->off = staging->bytes = 0;
   if (!make_room(sv, s.ring_bytes, keep)) return JEFI_ENOMEM;
   uint64_t off;
   if (!sv->darena.alloc(s.ring_bytes, &off)) return JEFI_ENOMEM;
+  const uint64_t sh_bytes = s.shadow.size();
+  uint64_t so = 0;
+  if (s.newest >= 0 && (!make_room(sv, sh_bytes, keep) || !sv->darena.alloc(sh_bytes, &so))) {
+    sv->darena.release(off, s.ring_bytes);
+    return JEFI_ENOMEM;
+  }
   s.ring_off = off;
   s.resident = true;
   jefi_history h{};
   const int dt = sv->cfg.precision == JEFI_PREC_F64 ? JEFI_F64 : JEFI_F32;
   jefi_status rc = jefi_history_init(&h, sv->dbase + off, s.ring_bytes, &s.src, s.capacity, dt, s.t0, st);
-  if (rc != JEFI_OK) return rc;
-  if (s.newest >= 0) {
-    const uint64_t sh_bytes = s.shadow.size();
-    uint64_t so, po;
-    if (!sv->parena.alloc(sh_bytes, &po)) {
-      sv->darena.release(s.ring_off, s.ring_bytes);
-      s.resident = false;
-      return JEFI_ENOMEM;
+  if (rc == JEFI_OK && s.newest >= 0) {
+    staging->off = so;
+    staging->bytes = sh_bytes;
+    hipError_t e = hipMemcpyAsync(sv->dbase + so, s.shadow.data(), sh_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      jefi::GridD g;
+      for (int a = 0; a < 3; ++a) {
+        g.n[a] = s.src.n[a];
+        g.o[a] = s.src.origin[a];
+        g.h[a] = s.src.spacing[a];
+      }
+      e = jefi::launch_ingest_slots(sv->dbase + so, sv->dbase + off, g, (g.n[0] + 1) / 2, (g.n[1] + 1) / 2, s.capacity,
+                              dt == JEFI_F64, st);
     }
-    if (!make_room(sv, sh_bytes, keep) || !sv->darena.alloc(sh_bytes, &so)) {
-      sv->parena.release(po, sh_bytes);
-      sv->darena.release(s.ring_off, s.ring_bytes);
-      s.resident = false;
-      return JEFI_ENOMEM;
-    }
-    b.extra.push_back({true, so, sh_bytes});
-    b.extra.push_back({false, po, sh_bytes});
-    std::memcpy(sv->pbase + po, s.shadow.data(), sh_bytes);
-    hipError_t e = hipMemcpyAsync(sv->dbase + so, sv->pbase + po, sh_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) {
       set_sticky(sv, e, "session upload");
-      return JEFI_EDEVICE;
-    }
-    const long long first = std::max<long long>(0, s.newest - s.capacity + 1);
-    h.newest = first - 1;
-    const size_t slice_bytes = (size_t)4 * s.n_src * s.elem;
-    for (long long step = first; step <= s.newest; ++step) {
-      const int slot = (int)(step % s.capacity);
-      rc = jefi_history_push(&h, &s.src, sv->dbase + so + slot * slice_bytes, st);
-      if (rc != JEFI_OK) return rc;
+      rc = JEFI_EDEVICE;
     }
     if (s.evicted) sv->stats.rematerialisations++;
   }
-  return JEFI_OK;
+  return rc;
 }
 
 void release_req(jefi_server* sv, Req& r) {
@@ -249,17 +249,25 @@ void complete_batch(jefi_server* sv, Batch& b, jefi_status st) {
 // scan (admission in arrival order).
 void admit_and_launch(jefi_server* sv) {
   if (sv->queue.empty()) return;
-  const int si = sv->next_stream;
+  // a stream with no batch in flight, so that this batch overlaps the others
+  int si = -1;
+  for (int i = 0; i < (int)sv->streams.size() && si < 0; ++i) {
+    bool used = false;
+    for (const Batch& f : sv->inflight) used = used || f.stream == i;
+    if (!used) si = i;
+  }
+  if (si < 0) return;
   hipStream_t st = sv->streams[si];
   Batch b;
   b.stream = si;
   std::unordered_set<uint64_t> in_batch;
   std::vector<uint64_t> chosen;
+  std::vector<hipEvent_t> deps;
   const size_t el = elem_size(sv->cfg.precision);
   for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)chosen.size() < sv->cfg.max_batch;) {
     Req& r = sv->reqs[*it];
     Session& s = sv->sessions[r.session];
-    if (s.busy > 0 || in_batch.count(s.id)) {
+    if (in_batch.count(s.id)) {  // one request per session and batch
       ++it;
       continue;
     }
@@ -276,7 +284,9 @@ void admit_and_launch(jefi_server* sv) {
     }
     in_batch.insert(s.id);
     if (!s.resident) {
-      jefi_status rc = materialise(sv, s, st, b, in_batch);
+      Region stg;
+      jefi_status rc = materialise(sv, s, st, in_batch, &stg);
+      if (stg.bytes) b.extra.push_back(stg);
       if (rc != JEFI_OK) {
         in_batch.erase(s.id);
         if (rc == JEFI_EDEVICE) return;
@@ -300,6 +310,11 @@ void admit_and_launch(jefi_server* sv) {
     }
     (void)el;
     if (slice_bytes) std::memcpy(sv->pbase + r.pin_off, r.slice.data(), slice_bytes);
+    // A session with a request still on the device: this batch's stream
+    // waits for that batch before its push and evaluation (the push may
+    // overwrite a slot the earlier evaluation reads).
+    if (s.busy > 0 && s.last_done && std::find(deps.begin(), deps.end(), s.last_done) == deps.end())
+      deps.push_back(s.last_done);
     r.t_admit = now_ns();
     r.state = kRunning;
     s.queued--;
@@ -322,6 +337,10 @@ void admit_and_launch(jefi_server* sv) {
     return;
   }
   // Launch: slice uploads and pushes, one batched evaluation, output copies.
+  for (hipEvent_t ev : deps) {
+    const hipError_t e = hipStreamWaitEvent(st, ev, 0);
+    if (e != hipSuccess) set_sticky(sv, e, "hipStreamWaitEvent");
+  }
   std::vector<jefi_problem> probs;
   probs.reserve(chosen.size());
   const uint64_t t_start = now_ns();
@@ -406,10 +425,10 @@ void admit_and_launch(jefi_server* sv) {
   sv->events.pop_back();
   hipError_t e = hipEventRecord(b.done, st);
   if (e != hipSuccess) set_sticky(sv, e, "hipEventRecord");
+  for (uint64_t tk : chosen) sv->sessions[sv->reqs[tk].session].last_done = b.done;
   sv->stats.batches++;
   if ((uint64_t)chosen.size() > sv->stats.max_batch) sv->stats.max_batch = chosen.size();
   sv->inflight.push_back(std::move(b));
-  sv->next_stream = (sv->next_stream + 1) % (int)sv->streams.size();
 }
 
 void scheduler(jefi_server* sv) {
@@ -475,6 +494,13 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
     }
     sv->streams.push_back(s);
   }
+  if (hipStreamCreateWithFlags(&sv->setup, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    for (hipStream_t x : sv->streams) (void)hipStreamDestroy(x);
+    (void)hipHostFree(sv->pbase);
+    delete sv;
+    return JEFI_EDEVICE;
+  }
   sv->stats.arena_bytes = cfg->arena_bytes;
   sv->th = std::thread(scheduler, sv);
   *out = sv;
@@ -511,7 +537,21 @@ jefi_status jefi_server_open_session(jefi_server* sv, uint64_t session, const je
                 slice_bytes);
   s.newest = init_nt - 1;
   s.last_use = ++sv->use_clock;
-  sv->sessions.emplace(session, std::move(s));
+  Session& ss = sv->sessions.emplace(session, std::move(s)).first->second;
+  // Upload the ring now when the arena has room (idle sessions may be
+  // evicted for it), so that the first request does not pay for it;
+  // otherwise the first admitted request brings it in.
+  Region stg;
+  const jefi_status rc = materialise(sv, ss, sv->setup, {}, &stg);
+  if (rc == JEFI_EDEVICE) return JEFI_EDEVICE;
+  if (rc == JEFI_OK || stg.bytes) {
+    const hipError_t e = hipStreamSynchronize(sv->setup);
+    if (e != hipSuccess) {
+      set_sticky(sv, e, "session upload");
+      return JEFI_EDEVICE;
+    }
+  }
+  if (stg.bytes) sv->darena.release(stg.off, stg.bytes);
   return JEFI_OK;
 }
 
@@ -536,7 +576,7 @@ jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t
   const uint64_t shadow_bytes = Arena::round_up(s.shadow.size());
   uint64_t need = Arena::round_up(s.ring_bytes) + shadow_bytes + Arena::round_up(out_bytes);
   if (rq->new_slice) need += Arena::round_up(slice_bytes);
-  const uint64_t pin_need = shadow_bytes + Arena::round_up(rq->new_slice ? slice_bytes : 0) + out_bytes;
+  const uint64_t pin_need = Arena::round_up(rq->new_slice ? slice_bytes : 0) + out_bytes;
   if (need > sv->cfg.arena_bytes || pin_need > sv->cfg.pinned_bytes) return JEFI_ETOOLARGE;
   Req r;
   r.ticket = sv->next_ticket++;
@@ -631,6 +671,7 @@ jefi_status jefi_server_destroy(jefi_server* sv) {
   sv->th.join();
   const jefi_status st = sv->sticky;
   for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+  (void)hipStreamDestroy(sv->setup);
   for (hipEvent_t e : sv->events) (void)hipEventDestroy(e);
   (void)hipHostFree(sv->pbase);
   delete sv;

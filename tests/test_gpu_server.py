@@ -61,15 +61,28 @@ def _solo(J, src, hist_window, dt, newest, obs, t, prec="f32"):
     return E[:, :obs.size].double().cpu().numpy(), B[:, :obs.size].double().cpu().numpy()
 
 
-def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32"):
+def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32", max_inflight=2,
+                blocker=False):
+    """n_req requests over n_sessions sessions, submitted back to back.
+    blocker: first submit one large request of an extra session, so that
+    (with max_inflight = 1) the others queue up behind it and are batched."""
     import torch
     rng = np.random.default_rng(seed)
     sess = _sessions(n_sessions, seed)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     f64 = prec == "f64"
     ndt = np.float64 if f64 else np.float32
-    sv = J.Server(arena, precision=J.JEFI_PREC_F64 if f64 else J.JEFI_PREC_F32_COMP, max_inflight=2,
+    sv = J.Server(arena, precision=J.JEFI_PREC_F64 if f64 else J.JEFI_PREC_F32_COMP, max_inflight=max_inflight,
                   max_batch=64)
+    if blocker:
+        bsrc = centred_grid((48, 48, 48), 1.6 / 48)
+        bh = blob_history(bsrc, workloads.draw_blobs(np.random.default_rng(1), 3, (-0.8, 0.8)), 8, 0.8 / 48)
+        sv.open_session(1, bsrc, 8, 8, 0.0, 0.8 / 48, bh.astype(ndt))
+        bobs = centred_grid((64, 64, 64), 1.6 / 48)
+        bE = np.empty((3, bobs.size), ndt)
+        bB = np.empty((3, bobs.size), ndt)
+        st, btk = sv.submit(1, bobs, bE, bB)
+        assert st == J.JEFI_OK
     full = {}
     for s in sess:
         steps = init_steps + n_req  # enough slices for every push
@@ -89,6 +102,9 @@ def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32
         assert st == J.JEFI_OK, J.jefi_last_error()
         reqs.append(dict(ticket=tk, sid=sid, newest=newest[sid], obs=obs, E=E, B=B, s=s))
     results = []
+    if blocker:
+        st, res = sv.wait(btk)
+        assert st == J.JEFI_OK and res.status == J.JEFI_OK
     for r in reqs:
         st, res = sv.wait(r["ticket"])
         assert st == J.JEFI_OK and res.status == J.JEFI_OK, (st, res.status)
@@ -121,16 +137,27 @@ def _check_solo(J, reqs, full, n_oracle=4, prec="f32"):
 
 
 def test_server_results_equal_solo_in_the_mix():
+    """Requests queued behind a large one are batched together (one stream
+    slot), and each result equals the same evaluation alone."""
     J = _gpu()
-    reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=6, n_req=60, seed=3)
-    assert stats["completed"] == 60 and stats["failed"] == 0
-    assert stats["batches"] >= 1
+    reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=6, n_req=60, seed=3, max_inflight=1,
+                                             blocker=True)
+    assert stats["completed"] == 61 and stats["failed"] == 0
     print(f"server: {stats['batches']} batches, largest {stats['max_batch']}", flush=True)
-    # requests were batched together (continuous batching, not one by one)
     assert max(r.batch_size for r in results) > 1
     for r in results:
         assert r.t_submit_ns <= r.t_admit_ns <= r.t_start_ns <= r.t_done_ns
     _check_solo(J, reqs, full)
+
+
+def test_server_overlapping_batches_keep_session_order():
+    """Several batches in flight on different streams, with later requests of
+    a session admitted while its earlier ones still run (stream-ordered by
+    events): every result equals the same evaluation alone."""
+    J = _gpu()
+    reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=3, n_req=45, seed=13, max_inflight=4)
+    assert stats["completed"] == 45 and stats["failed"] == 0
+    _check_solo(J, reqs, full, n_oracle=2)
 
 
 def test_server_fp64_results_equal_solo():
