@@ -567,7 +567,6 @@ jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t
   auto sit = sv->sessions.find(rq->session);
   if (sit == sv->sessions.end()) return JEFI_ENOENT;
   Session& s = sit->second;
-  if ((int)sv->queue.size() >= sv->cfg.max_queue) return JEFI_EBUSY;
   const size_t slice_bytes = (size_t)4 * s.n_src * s.elem;
   const uint64_t out_bytes = rq->out_on_host ? (uint64_t)6 * n_obs * (rq->out_dtype == JEFI_F64 ? 8 : 4) : 0;
   // Worst case for one request on an otherwise empty arena: the ring, the
@@ -578,6 +577,8 @@ jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t
   if (rq->new_slice) need += Arena::round_up(slice_bytes);
   const uint64_t pin_need = Arena::round_up(rq->new_slice ? slice_bytes : 0) + out_bytes;
   if (need > sv->cfg.arena_bytes || pin_need > sv->cfg.pinned_bytes) return JEFI_ETOOLARGE;
+  // only requests that could ever run are told to retry
+  if ((int)sv->queue.size() >= sv->cfg.max_queue) return JEFI_EBUSY;
   Req r;
   r.ticket = sv->next_ticket++;
   r.session = rq->session;

@@ -1,0 +1,270 @@
+// CPU test of the serving loop (jefi_server.cpp) against the host mock of
+// the HIP runtime and of the library calls (server_mock.cpp): concurrent
+// submitters, overlapping batches and per-session ordering of pushes and
+// evaluations, eviction and re-materialisation, a full queue, requests that
+// can never fit, session closing, timestamps.  Built with ThreadSanitizer.
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <thread>
+#include <vector>
+
+#include "../../include/libjefi.h"
+
+extern int g_eval_sleep_us;
+
+static std::atomic<int> g_fail{0};
+#define CHECK(c)                                                \
+  do {                                                          \
+    if (!(c)) {                                                 \
+      std::printf("FAIL %s:%d %s\n", __FILE__, __LINE__, #c);  \
+      g_fail.fetch_add(1);                                      \
+    }                                                           \
+  } while (0)
+
+namespace {
+
+constexpr int kCap = 6;  // ring capacity = evaluation window: a push reuses the slot the previous window began with
+
+jefi_grid grid(int n) {
+  jefi_grid g;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = n;
+    g.origin[a] = -0.5;
+    g.spacing[a] = 1.0 / n;
+  }
+  return g;
+}
+
+float value(int sid, long long step) { return step < 0 ? 0.0f : (float)(1000 * sid + step); }
+
+// What the mock evaluation reports for a session whose newest step is `newest`.
+double expected(int sid, long long newest) {
+  const long long nt = std::min<long long>(kCap, newest + 1);
+  double acc = 0.0;
+  for (long long j = 0; j < nt; ++j) acc += (double)(j + 1) * value(sid, newest - nt + 1 + j);
+  return acc;
+}
+
+struct Session {
+  int sid;
+  int edge;
+  long long next_step;
+};
+
+struct Pending {
+  int sid;
+  long long step;
+  uint64_t ticket;
+  std::vector<float> E, B;
+  std::vector<float> slice;
+};
+
+jefi_server* make_server(size_t arena_bytes, int max_inflight, int max_queue, std::vector<char>& arena) {
+  arena.assign(arena_bytes, 0);
+  jefi_server_config cfg;
+  std::memset(&cfg, 0, sizeof cfg);
+  cfg.arena = arena.data();
+  cfg.arena_bytes = arena_bytes;
+  cfg.precision = JEFI_PREC_F32_COMP;
+  cfg.max_inflight = max_inflight;
+  cfg.max_batch = 64;
+  cfg.max_queue = max_queue;
+  jefi_server* sv = nullptr;
+  CHECK(jefi_server_create(&cfg, &sv) == JEFI_OK);
+  return sv;
+}
+
+void open_sessions(jefi_server* sv, std::vector<Session>& ss, int init_nt) {
+  for (Session& s : ss) {
+    const jefi_grid g = grid(s.edge);
+    const long long n = (long long)s.edge * s.edge * s.edge;
+    std::vector<float> h((size_t)init_nt * 4 * n);
+    for (int k = 0; k < init_nt; ++k)
+      for (long long i = 0; i < 4 * n; ++i) h[(size_t)k * 4 * n + i] = value(s.sid, k);
+    CHECK(jefi_server_open_session(sv, (uint64_t)s.sid, &g, kCap, kCap, 0.0, 0.1, h.data(), init_nt) == JEFI_OK);
+    s.next_step = init_nt;
+  }
+}
+
+// Submit one request (retrying while the queue is full); returns 0 or the
+// number of EBUSY answers seen.
+int submit(jefi_server* sv, Session& s, Pending& p, int n_obs_edge) {
+  const jefi_grid g = grid(s.edge);
+  const long long n = (long long)s.edge * s.edge * s.edge;
+  p.sid = s.sid;
+  p.step = s.next_step++;
+  p.slice.assign((size_t)4 * n, value(s.sid, p.step));
+  const jefi_grid obs = grid(n_obs_edge);
+  const long long no = (long long)n_obs_edge * n_obs_edge * n_obs_edge;
+  p.E.assign((size_t)3 * no, NAN);
+  p.B.assign((size_t)3 * no, NAN);
+  jefi_request rq;
+  std::memset(&rq, 0, sizeof rq);
+  rq.session = (uint64_t)s.sid;
+  rq.new_slice = p.slice.data();
+  rq.obs = obs;
+  rq.t = NAN;
+  rq.E = p.E.data();
+  rq.B = p.B.data();
+  rq.out_dtype = JEFI_F32;
+  rq.out_on_host = 1;
+  int busy = 0;
+  for (;;) {
+    const jefi_status st = jefi_server_submit(sv, &rq, &p.ticket);
+    if (st == JEFI_OK) break;
+    CHECK(st == JEFI_EBUSY);
+    if (st != JEFI_EBUSY) break;
+    ++busy;
+    std::this_thread::sleep_for(std::chrono::microseconds(200));
+  }
+  (void)g;
+  return busy;
+}
+
+void check_result(jefi_server* sv, Pending& p) {
+  jefi_result res;
+  CHECK(jefi_server_wait(sv, p.ticket, &res) == JEFI_OK);
+  CHECK(res.status == JEFI_OK);
+  CHECK(res.t_submit_ns <= res.t_admit_ns && res.t_admit_ns <= res.t_start_ns && res.t_start_ns <= res.t_done_ns);
+  CHECK(res.batch_size >= 1);
+  const size_t no = p.E.size() / 3;
+  const double want = expected(p.sid, p.step);
+  for (size_t o = 0; o < no; ++o) {
+    // the weighted sums are integers below 2^24: exact in FP32
+    if (p.E[o] != (float)want || p.E[no + o] != (float)p.step ||
+        p.B[o] != (float)o) {
+      std::printf("FAIL session %d step %lld point %zu: E0 %g want %g, E1 %g\n", p.sid, p.step, o, p.E[o], want,
+                  p.E[no + o]);
+      g_fail.fetch_add(1);
+      return;
+    }
+  }
+}
+
+void concurrent_submitters() {
+  std::vector<char> arena;
+  jefi_server* sv = make_server(64 << 20, 3, 65536, arena);
+  g_eval_sleep_us = 150;
+  std::vector<Session> a = {{1, 3, 0}, {2, 4, 0}, {3, 5, 0}}, b = {{4, 6, 0}, {5, 2, 0}};
+  open_sessions(sv, a, 3);
+  open_sessions(sv, b, 2);
+  auto worker = [&](std::vector<Session>& ss, unsigned seed, int count) {
+    std::mt19937 rng(seed);
+    std::vector<Pending> ps((size_t)count);
+    for (int i = 0; i < count; ++i) submit(sv, ss[rng() % ss.size()], ps[(size_t)i], 1 + (int)(rng() % 3));
+    for (Pending& p : ps) check_result(sv, p);
+  };
+  std::thread t1(worker, std::ref(a), 1u, 150);
+  std::thread t2(worker, std::ref(b), 2u, 120);
+  t1.join();
+  t2.join();
+  jefi_server_stats st;
+  CHECK(jefi_server_get_stats(sv, &st) == JEFI_OK);
+  CHECK(st.completed == 270 && st.failed == 0 && st.submitted == 270);
+  CHECK(st.batches >= 1 && st.max_batch >= 2);
+  std::printf("concurrent: %llu batches, largest %llu\n", (unsigned long long)st.batches,
+              (unsigned long long)st.max_batch);
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
+void eviction() {
+  // rings of 10^3 cells: 6 slots x 4 channels x 1000 x 4 B = 96 000 B, the
+  // shadow staging as much again; room for about two sessions at once
+  std::vector<char> arena;
+  jefi_server* sv = make_server(330 * 1024, 2, 65536, arena);
+  g_eval_sleep_us = 50;
+  std::vector<Session> ss = {{11, 10, 0}, {12, 10, 0}, {13, 10, 0}, {14, 10, 0}, {15, 10, 0}};
+  open_sessions(sv, ss, 4);
+  std::vector<Pending> ps(60);
+  for (int i = 0; i < 60; ++i) submit(sv, ss[(size_t)(i * 7 % 5)], ps[(size_t)i], 2);
+  for (Pending& p : ps) check_result(sv, p);
+  jefi_server_stats st;
+  CHECK(jefi_server_get_stats(sv, &st) == JEFI_OK);
+  CHECK(st.evictions > 0 && st.rematerialisations > 0);
+  CHECK(st.arena_high_water <= 330 * 1024);
+  std::printf("eviction: %llu evictions, %llu rematerialisations\n", (unsigned long long)st.evictions,
+              (unsigned long long)st.rematerialisations);
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
+void full_queue_and_rejections() {
+  std::vector<char> arena;
+  jefi_server* sv = make_server(8 << 20, 1, 3, arena);
+  g_eval_sleep_us = 3000;
+  std::vector<Session> ss = {{21, 3, 0}, {22, 3, 0}, {23, 3, 0}, {24, 3, 0}};
+  open_sessions(sv, ss, 1);
+  std::vector<Pending> ps(24);
+  int busy = 0;
+  for (int i = 0; i < 24; ++i) busy += submit(sv, ss[(size_t)(i % 4)], ps[(size_t)i], 1);
+  CHECK(busy > 0);  // the queue of 3 filled up at least once
+  // unknown session, request that can never fit the arena
+  jefi_request rq;
+  std::memset(&rq, 0, sizeof rq);
+  std::vector<float> E(3), B(3);
+  rq.session = 99;
+  rq.obs = grid(1);
+  rq.t = NAN;
+  rq.E = E.data();
+  rq.B = B.data();
+  rq.out_on_host = 1;
+  uint64_t tk;
+  CHECK(jefi_server_submit(sv, &rq, &tk) == JEFI_ENOENT);
+  rq.session = 21;
+  rq.obs = grid(400);  // 6.4e7 points: outputs far beyond the arena
+  CHECK(jefi_server_submit(sv, &rq, &tk) == JEFI_ETOOLARGE);
+  // closing a session with requests outstanding is refused
+  CHECK(jefi_server_close_session(sv, 24) == JEFI_EBUSY);
+  for (Pending& p : ps) check_result(sv, p);
+  CHECK(jefi_server_close_session(sv, 24) == JEFI_OK);
+  CHECK(jefi_server_close_session(sv, 24) == JEFI_ENOENT);
+  rq.session = 24;
+  rq.obs = grid(1);
+  CHECK(jefi_server_submit(sv, &rq, &tk) == JEFI_ENOENT);
+  jefi_server_stats st;
+  CHECK(jefi_server_get_stats(sv, &st) == JEFI_OK);
+  CHECK(st.completed == 24 && st.failed == 0);
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
+void time_after_newest_fails_at_admission() {
+  std::vector<char> arena;
+  jefi_server* sv = make_server(8 << 20, 2, 64, arena);
+  g_eval_sleep_us = 0;
+  std::vector<Session> ss = {{31, 3, 0}};
+  open_sessions(sv, ss, 2);
+  jefi_request rq;
+  std::memset(&rq, 0, sizeof rq);
+  std::vector<float> E(3), B(3);
+  rq.session = 31;
+  rq.obs = grid(1);
+  rq.t = 100.0;  // step 1000 of a session whose newest step is 1
+  rq.E = E.data();
+  rq.B = B.data();
+  rq.out_on_host = 1;
+  uint64_t tk;
+  CHECK(jefi_server_submit(sv, &rq, &tk) == JEFI_OK);
+  jefi_result res;
+  CHECK(jefi_server_wait(sv, tk, &res) == JEFI_OK);
+  CHECK(res.status == JEFI_EINVAL);
+  // the session still serves later requests
+  Pending p;
+  submit(sv, ss[0], p, 2);
+  check_result(sv, p);
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
+}  // namespace
+
+int main() {
+  std::setvbuf(stdout, nullptr, _IONBF, 0);
+  concurrent_submitters();
+  eviction();
+  full_queue_and_rejections();
+  time_after_newest_fails_at_admission();
+  if (g_fail.load() == 0) std::printf("server ok\n");
+  return g_fail.load() == 0 ? 0 : 1;
+}
