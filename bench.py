@@ -118,6 +118,38 @@ def run_path(p, extra, prec, steps, warmup):
     return out
 
 
+def run_companion(args):
+    """The 32^3 x 32^3 single instance (64 slices, 20 blobs, coincident
+    grids), FP32-comp against FP64 on the same GPU, reported beside the 64^3
+    headline, with its parity against the oracle on sampled points."""
+    import workloads
+    import oracle
+    from oracle.compare import max_rel_l2
+    p = workloads.config_medium()
+    K, W = 20, 3
+    extra = workloads.blob_history(p.src, p.blobs, list(range(p.newest + 1, p.newest + 1 + W + K)), p.dt, p.t0)
+    r32 = run_path(p, extra, "f32", K, W)
+    r64 = run_path(p, extra, "f64", K, W)
+    pairs = p.src.size * p.obs.size
+    full = np.concatenate([p.hist, extra], axis=0)
+    last = r32["newest"]
+    win = full[last - p.nt + 1:last + 1]
+    sel = np.sort(np.random.default_rng(12).choice(p.obs.size, size=32, replace=False))
+    Er, Br = oracle.eval_fields(p.src, p.obs, win, p.dt, p.t0 + last * p.dt, p.t0, last, p.c, p.screen, sel=sel)
+    e32 = max_rel_l2(r32["E"][:, sel], r32["B"][:, sel], Er, Br)
+    e64 = max_rel_l2(r64["E"][:, sel], r64["B"][:, sel], Er, Br)
+    v32 = pairs * K / r32["wall_s"] / 1e9
+    v64 = pairs * K / r64["wall_s"] / 1e9
+    log(f"32^3 companion: f32 {v32:.1f} G pairs/s, f64 {v64:.1f} G pairs/s, parity {e32:.2e} / {e64:.2e}")
+    return {"workload": p.name, "value": round(v32, 3), "unit": "G pairs/s", "steps": K,
+            "ms_per_step": round(r32["wall_s"] * 1e3 / K, 4),
+            "eval_ms_p50": round(float(np.percentile(r32["eval_ms"], 50)), 4),
+            "eval_ms_p99": round(float(np.percentile(r32["eval_ms"], 99)), 4),
+            "fp64_path": round(v64, 3), "fp32_over_fp64": round(v32 / v64, 3),
+            "parity": {"max_rel_l2_f32": float(f"{e32:.3e}"), "max_rel_l2_f64": float(f"{e64:.3e}"),
+                       "ok": bool(e32 <= 1e-5 and e64 <= 1e-12)}}
+
+
 def run_batch_workload(args):
     """64 uneven instances: one push per instance and one batched persistent
     evaluation per step, against one launch per instance (FP32 and FP64)."""
@@ -380,6 +412,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-companion", action="store_true",
+                    help="skip the 32^3 single-instance line reported beside the 64^3 headline")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the request stream for --workload serve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -469,6 +503,9 @@ def main():
                      "flops_per_live_pair": FLOPS_PER_LIVE_PAIR},
     }
 
+    if args.workload == "large" and not args.no_companion:
+        res["single_instance_32^3"] = run_companion(args)
+
     if not args.no_parity or not args.no_cpu_baseline:
         import oracle
         # history window of the final state: the last nt steps
@@ -503,7 +540,9 @@ def main():
 
     if not args.no_cpu_baseline:
         threads = oracle.max_threads()
-        probe = np.arange(0, p.obs.size, max(1, p.obs.size // 4))[:4]
+        # enough probe points to occupy every thread, so the rate is the parallel one
+        n_probe = min(p.obs.size, 4 * threads)
+        probe = np.linspace(0, p.obs.size - 1, n_probe).astype(np.int64)
         t0 = time.perf_counter()
         oracle.eval_fields(p.src, p.obs, win, p.dt, t_last, p.t0, last, p.c, p.screen, sel=probe)
         rate = len(probe) * p.src.size / max(time.perf_counter() - t0, 1e-6)
