@@ -262,6 +262,8 @@ bool guard_pairs_common(const jefi_grid* src, const jefi_grid* obs, const TimeSp
   return hits * 700 >= kSamples;  // about 1.4e-3
 }
 
+constexpr long long kMinRounds = 32;
+
 // Everything about a launch except the history pointer and outputs.
 // `splits_target_wg`: workgroups to aim for (single launches) or 0 to
 // leave n_splits = 1 for the caller to set.
@@ -360,7 +362,11 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
 
   if (splits_target_wg > 0) {
     long long splits = (splits_target_wg + p.n_tiles - 1) / p.n_tiles;
-    long long max_splits = p.n_bricks / 8 > 0 ? p.n_bricks / 8 : 1;
+    // at least kMinRounds staging rounds per workgroup, so that its set-up
+    // (tile geometry, threshold table, first window) stays small
+    const long long g = (r.precision == JEFI_PREC_F64 ? 1 : 2) * (p.tile_z == 8 ? 2 : 1);
+    long long max_splits = p.n_bricks / (kMinRounds * g);
+    if (max_splits < 1) max_splits = 1;
     if (splits > max_splits) splits = max_splits;
     if (splits < 1) splits = 1;
     long long bps = (p.n_bricks + splits - 1) / splits;
@@ -484,7 +490,11 @@ void attach_history(PairParams& p, const jefi_history* hist, int nt) {
   p.ring_bytes_rs = rb < 0x7ffffff0ull ? (unsigned)rb : 0u;
 }
 
-long long single_target_wg(int tile_z) { return tile_z == 8 ? 8192 : 16384; }
+// Workgroups to aim for in a single launch: many waves of them over the
+// 256 CUs, so that the cheap tiles (mostly culled) and the expensive ones
+// even out at the end; split partials grow with it (6 doubles per point and
+// split), which stays far below the time it saves on the 64^3 workload.
+long long single_target_wg(int tile_z) { return tile_z == 8 ? 32768 : 65536; }
 
 // ---- batched evaluation ----------------------------------------------------------
 struct BatchWorkspace {
