@@ -795,6 +795,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   const int iy = tg.iy0 + ((w >> 1) & 1) * 4 + ((l >> 2) & 3);
   const int iz = tg.iz0 + (w >> 2) * 4 + (l >> 4);
   const bool valid = ix <= tg.ix1 && iy <= tg.iy1 && iz <= tg.iz1;
+  const bool wave_live = __any(valid);
   const int cix = min(ix, tg.ix1), ciy = min(iy, tg.iy1), ciz = min(iz, tg.iz1);
   const double rox = canon(p.obs.o[0], cix, p.obs.h[0]);
   const double roy = canon(p.obs.o[1], ciy, p.obs.h[1]);
@@ -897,6 +898,9 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     __syncthreads();
     if (rb + G < b_end) load_round(buf ^ 1);
 
+    // a wavefront whose 4x4x4 block lies wholly outside the observation
+    // grid (tile padding) stages but computes nothing
+    if (wave_live) {
     float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
     if constexpr (sizeof(T) == 4) {
       // Full far bricks first (all 8 cells, no screening possible), then the
@@ -1108,6 +1112,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           pair_fields(lds, PU, e, u - fl, R, dx[cx], dy[cy], dz[cz], dE, dB);
         }
       }
+    }
     }
     __syncthreads();
     buf ^= 1;
