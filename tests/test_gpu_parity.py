@@ -180,6 +180,29 @@ def test_ragged_random_problems(seed):
             assert np.array_equal(G.gpu_fingerprint(p, prec, tile=tile), fp_ref)
 
 
+@pytest.mark.parametrize("seed", [3, 5])
+def test_large_step_numbers(seed):
+    """The window starts at step ~3e7 (t/dt ~ 3e7, far beyond FP32's integer
+    range; the time origin keeps the blobs in view): the FP64 split of the
+    evaluation time keeps both paths exact."""
+    G = _gpu()
+    base = _ragged_problem(seed)
+    rng = np.random.default_rng(seed)
+    s_old = int(rng.integers(2 * 10 ** 7, 4 * 10 ** 7))
+    newest = s_old + base.nt - 1
+    t0 = -s_old * base.dt
+    blobs = workloads.draw_blobs(rng, 3, (-0.5, 0.3))
+    hist = blob_history(base.src, blobs, list(range(s_old, newest + 1)), base.dt, t0)
+    t = t0 + newest * base.dt - 0.37 * base.dt
+    p = Problem(f"bigstep{seed}", base.src, base.obs, hist, base.dt, t, t0, newest, base.c, base.screen)
+    Er, Br = oracle.eval_problem(p)
+    fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+    for prec in ["f64", "f32"]:
+        Eg, Bg = G.gpu_eval(p, prec)
+        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"{p.name} {prec}")
+        assert np.array_equal(G.gpu_fingerprint(p, prec), fp_ref)
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_rough_histories_fp64(seed):
     """White-noise histories (no smoothness to hide interpolation mistakes)."""
