@@ -36,6 +36,11 @@
  *   - Every function returns jefi_status; on an error nothing is written to
  *     the outputs and jefi_last_error() explains (thread-local text).
  *     JEFI_EDEVICE after a HIP failure is sticky for the process.
+ *   - Threads: any number of host threads may call the library on different
+ *     streams at once.  The library keeps scratch memory per (device,
+ *     stream), so calls on one stream must come from one host thread at a
+ *     time (as stream order already implies).  The serving loop (below) is
+ *     safe to use from any thread.
  */
 #ifndef LIBJEFI_H
 #define LIBJEFI_H
