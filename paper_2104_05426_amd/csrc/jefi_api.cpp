@@ -216,7 +216,8 @@ void grid_box(const jefi_grid* g, double lo[3], double hi[3]) {
 
 struct Plan {
   PairParams p;
-  int multi;
+  int multi;  // window longer than any staging shape: the chunked kernel
+  int wsel;   // slots staged per cell otherwise (32, 64, 128)
   bool all_dead;
   bool empty;
 };
@@ -276,6 +277,7 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   PairParams& p = plan->p;
   std::memset(&p, 0, sizeof p);
   plan->multi = 0;
+  plan->wsel = 32;
   plan->all_dead = ts.a_i <= -2;  // every pair's stencil lies before the oldest slice
   p.src = to_gd(src);
   p.obs = to_gd(obs);
@@ -357,14 +359,22 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
     p.exact_idx = r.flags == JEFI_FLAG_INDEX_TABLE || guard_pairs_common(src, obs, ts, g) ? 1 : 0;
   // Longest slice window any brick can need (the 8x8x8 tile bounds both shapes).
   const double wb = std::floor((diam_t + diam_b) * ts.inv_cdt * (1.0 + 1e-12) + 2.0 * p.margin + 1e-6) + 3.0;
-  plan->multi = !(wb <= (double)kWmax);
-  if (plan->multi) set_tiles(p, obs, 8);  // the chunked kernel runs 8x8x8 tiles only
+  // Staging shape: 32 slots per cell, else 64 or 128 with fewer bricks per
+  // round (8x8x8 tiles; FP64 stops at 64), else the chunked kernel.
+  const int wcap = r.precision == JEFI_PREC_F64 ? 64 : 128;
+  plan->wsel = 0;
+  for (int w = 32; w <= wcap && plan->wsel == 0; w *= 2)
+    if (wb <= (double)w) plan->wsel = w;
+  plan->multi = plan->wsel == 0;
+  if (plan->multi || plan->wsel > 32) set_tiles(p, obs, 8);  // those kernels run 8x8x8 tiles only
 
   if (splits_target_wg > 0) {
     long long splits = (splits_target_wg + p.n_tiles - 1) / p.n_tiles;
     // at least kMinRounds staging rounds per workgroup, so that its set-up
     // (tile geometry, threshold table, first window) stays small
-    const long long g = (r.precision == JEFI_PREC_F64 ? 1 : 2) * (p.tile_z == 8 ? 2 : 1);
+    const int w = plan->multi ? 32 : plan->wsel;
+    long long g = (long long)(r.precision == JEFI_PREC_F64 ? 1 : 2) * (p.tile_z == 8 ? 2 : 1) * 32 / w;
+    if (g < 1) g = 1;
     long long max_splits = p.n_bricks / (kMinRounds * g);
     if (max_splits < 1) max_splits = 1;
     if (splits > max_splits) splits = max_splits;
@@ -680,7 +690,7 @@ jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, dou
   } else {
     p.use_thr = 0;
   }
-  hipError_t e = launch_pairs(p, c.r.precision == JEFI_PREC_F64, 0, c.plan.multi, s);
+  hipError_t e = launch_pairs(p, c.r.precision == JEFI_PREC_F64, 0, c.plan.multi, c.plan.wsel, s);
   if (e != hipSuccess) return hip_fail(e, "pair kernel launch");
   if (!p.direct) {
     EpilogueParams ep{p.partial, p.n_splits, c.no, p.pref, out->E, out->B, out_f64};
@@ -747,7 +757,7 @@ jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* his
   } else {
     p.use_thr = 0;
   }
-  e = launch_pairs(p, c.r.precision == JEFI_PREC_F64, 1, c.plan.multi, s);
+  e = launch_pairs(p, c.r.precision == JEFI_PREC_F64, 1, c.plan.multi, c.plan.wsel, s);
   return e == hipSuccess ? JEFI_OK : hip_fail(e, "fingerprint kernel launch");
 }
 
@@ -789,7 +799,8 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
       if (e != hipSuccess) return hip_fail(e, "zero-fill launch");
       continue;
     }
-    if (c.plan.multi) {
+    if (c.plan.multi || c.plan.wsel > 32) {
+      // windows longer than the persistent kernel's 32 slots: their own launch
       jefi_status st = jefi_eval_fields(&q.src, &q.hist, q.dt, q.nt, &q.obs, q.t, &q.out, opt, stream);
       if (st != JEFI_OK) return st;
       continue;

@@ -15,7 +15,7 @@ constexpr int kThreads = 512;
 // Slice-window slots staged per source cell and launch variant.
 constexpr int kWmax = 32;
 // Largest table of slice-boundary thresholds a launch stages in LDS.
-constexpr int kThrMax = 512;
+constexpr int kThrMax = 1024;
 
 struct GridD {
   int n[3];
@@ -103,7 +103,9 @@ hipError_t launch_ingest(const void* slice, void* slot, const GridD& src, int nb
 // memory) into the first n_slots ring slots.
 hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, int nbx, int nby, int n_slots,
                                int is_f64, hipStream_t s);
-hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk,
+// wsel: slots staged per cell (32; 64 or 128 for long windows, 8x8x8 tiles
+// only, 64 at most in FP64); ignored when multi_chunk.
+hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk, int wsel,
                         hipStream_t s);
 hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt, hipStream_t s);
 // Kernel entry points of a batched evaluation, for graph nodes.

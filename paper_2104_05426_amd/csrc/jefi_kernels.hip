@@ -574,7 +574,6 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
 // outside the screening range take a two-phase path: slice decisions for all
 // 8 cells first (one divergent FP64 fix-up if any falls in the guard band),
 // then branch-free LDS reads and field arithmetic.
-constexpr int kCellStride = kWmax + 1;
 
 struct D4 {
   double x, y, z, w;
@@ -751,13 +750,18 @@ struct FpAcc {
   }
 };
 
-template <typename T, int WZ>
+// Launch shape: WZ = 1 (8x8x4 tiles, 256 threads) or 2 (8x8x8, 512 threads);
+// W = slots staged per cell (32, 64 or 128) -- the longer the window, the
+// fewer bricks fit a round in the same LDS.
+template <typename T, int WZ, int W>
 struct FastShape {
-  static constexpr int G = (sizeof(T) == 4 ? 2 : 1) * WZ;  // bricks per round
-  static constexpr int KT = 256 * WZ;                      // threads
+  static constexpr int G = (sizeof(T) == 4 ? 2 : 1) * WZ * 32 / W;  // bricks per round
+  static constexpr int KT = 256 * WZ;                                // threads
   static constexpr int NPL = Traits<T>::kPlanes;
-  static constexpr int PU = G * kBrickCells * kCellStride;  // 16-byte units per plane
+  static constexpr int CS = W + 1;                           // cell stride in entries (one pad entry)
+  static constexpr int PU = G * kBrickCells * CS;            // 16-byte units per plane
   static constexpr int THR = sizeof(T) == 4 ? kThrMax : 1;
+  static_assert(G >= 1, "window too long for this shape");
 };
 
 // One workgroup's share of a launch: tile x source split number `bid` of
@@ -766,21 +770,22 @@ struct FastShape {
 // 1 = threshold-table decision for every pair of a full brick.  PP is
 // PairParams as a kernel argument, or in the constant address space for
 // the persistent kernel (uniform, read-only: scalar loads).
-template <typename T, int WZ, bool FP, int IDX, class PP>
+template <typename T, int WZ, bool FP, int IDX, int W, class PP>
 __device__ __forceinline__ void pair_body(const PP& p, int bid,
-                                          float4 (&lds)[FastShape<T, WZ>::NPL * FastShape<T, WZ>::PU],
-                                          int4 (&tab_i)[2][FastShape<T, WZ>::G],
-                                          float4 (&tab_f)[2][FastShape<T, WZ>::G],
-                                          double (&tab_c)[2][FastShape<T, WZ>::G][6],
-                                          double (&thr)[FastShape<T, WZ>::THR]) {
+                                          float4 (&lds)[FastShape<T, WZ, W>::NPL * FastShape<T, WZ, W>::PU],
+                                          int4 (&tab_i)[2][FastShape<T, WZ, W>::G],
+                                          float4 (&tab_f)[2][FastShape<T, WZ, W>::G],
+                                          double (&tab_c)[2][FastShape<T, WZ, W>::G][6],
+                                          double (&thr)[FastShape<T, WZ, W>::THR]) {
   using Raw = typename RawOf<T>::type;
-  constexpr int G = FastShape<T, WZ>::G;
-  constexpr int kThreads = FastShape<T, WZ>::KT;
-  constexpr int PU = FastShape<T, WZ>::PU;
-  constexpr int EPT = G * kBrickCells * kWmax / kThreads;  // staged entries per thread
+  constexpr int G = FastShape<T, WZ, W>::G;
+  constexpr int kThreads = FastShape<T, WZ, W>::KT;
+  constexpr int PU = FastShape<T, WZ, W>::PU;
+  constexpr int kCellStride = FastShape<T, WZ, W>::CS;
+  constexpr int EPT = G * kBrickCells * W / kThreads;  // staged entries per thread
   constexpr int NRAW = EPT + 2;
-  constexpr int NQ = kWmax / EPT;
-  static_assert(EPT >= 1 && EPT * kThreads == G * kBrickCells * kWmax, "staging map");
+  constexpr int NQ = W / EPT;
+  static_assert(EPT >= 1 && EPT * kThreads == G * kBrickCells * W, "staging map");
 
   const int split = bid / p.n_tiles;
   const int tile = bid - split * p.n_tiles;
@@ -1029,7 +1034,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         if (!(slow & 1u)) continue;
         const int4 ti = tab_i[buf][j];
         const int lo = ti.x;
-        const int hiw = min(ti.y - lo, kWmax - 1);
+        const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;
         const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
         const int mlo = -off, mhi = hiw - off;
@@ -1073,7 +1078,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         const int4 ti = tab_i[buf][j];
         if (ti.z & 1) continue;
         const int lo = ti.x;
-        const int hiw = min(ti.y - lo, kWmax - 1);
+        const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;
         const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
         const int mlo = -off, mhi = hiw - off;
@@ -1156,15 +1161,15 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   }
 }
 
-template <typename T, int WZ, bool FP, int IDX>
+template <typename T, int WZ, bool FP, int IDX, int W>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
-  using S = FastShape<T, WZ>;
+  using S = FastShape<T, WZ, W>;
   __shared__ float4 lds[S::NPL * S::PU];
   __shared__ int4 tab_i[2][S::G];
   __shared__ float4 tab_f[2][S::G];
   __shared__ double tab_c[2][S::G][6];
   __shared__ double thr[S::THR];
-  pair_body<T, WZ, FP, IDX>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr);
+  pair_body<T, WZ, FP, IDX, W>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr);
 }
 
 // Persistent batched launch: workgroups pull (instance, workgroup id) items
@@ -1172,7 +1177,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
 // pair_body, one value for the whole batch.
 template <typename T, int WZ, int IDX>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_persistent(BatchDevice bd) {
-  using S = FastShape<T, WZ>;
+  using S = FastShape<T, WZ, 32>;
   __shared__ float4 lds[S::NPL * S::PU];
   __shared__ int4 tab_i[2][S::G];
   __shared__ float4 tab_f[2][S::G];
@@ -1191,7 +1196,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
     using CP = const __attribute__((address_space(4))) PairParams;
     CP& p = *(CP*)(bd.params + inst);
-    pair_body<T, WZ, false, IDX>(p, bid, lds, tab_i, tab_f, tab_c, thr);
+    pair_body<T, WZ, false, IDX, 32>(p, bid, lds, tab_i, tab_f, tab_c, thr);
   }
 }
 
@@ -1432,32 +1437,43 @@ hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, i
   return hipSuccess;
 }
 
-hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk,
+hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk, int wsel,
                         hipStream_t s) {
   dim3 grid(p.n_wg), block(kThreads);
 #define JEFI_LAUNCH(T, G, FPM, MUL) \
   hipLaunchKernelGGL((pair_kernel<T, G, FPM, MUL>), grid, block, 0, s, p)
-#define JEFI_FAST(T, WZ, FPM, IDX) \
-  hipLaunchKernelGGL((pair_kernel_fast<T, WZ, FPM, IDX>), grid, dim3(256 * WZ), 0, s, p)
-#define JEFI_FAST_F32(WZ, FPM) \
+#define JEFI_FAST(T, WZ, FPM, IDX, W) \
+  hipLaunchKernelGGL((pair_kernel_fast<T, WZ, FPM, IDX, W>), grid, dim3(256 * WZ), 0, s, p)
+#define JEFI_FAST_F32(WZ, FPM, W)        \
   do {                                  \
     if (p.exact_idx)                    \
-      JEFI_FAST(float, WZ, FPM, 1);     \
+      JEFI_FAST(float, WZ, FPM, 1, W);  \
     else                                \
-      JEFI_FAST(float, WZ, FPM, 0);     \
+      JEFI_FAST(float, WZ, FPM, 0, W);  \
   } while (0)
+  if (!multi_chunk && wsel > 32) {
+    // long windows: 8x8x8 tiles, fewer bricks per round
+    if (is_f64) {
+      if (fingerprint) JEFI_FAST(double, 2, true, 0, 64); else JEFI_FAST(double, 2, false, 0, 64);
+    } else if (wsel == 64) {
+      if (fingerprint) JEFI_FAST_F32(2, true, 64); else JEFI_FAST_F32(2, false, 64);
+    } else {
+      if (fingerprint) JEFI_FAST_F32(2, true, 128); else JEFI_FAST_F32(2, false, 128);
+    }
+    return hipGetLastError();
+  }
   if (!multi_chunk) {
     if (p.tile_z == 8) {
       if (is_f64) {
-        if (fingerprint) JEFI_FAST(double, 2, true, 0); else JEFI_FAST(double, 2, false, 0);
+        if (fingerprint) JEFI_FAST(double, 2, true, 0, 32); else JEFI_FAST(double, 2, false, 0, 32);
       } else {
-        if (fingerprint) JEFI_FAST_F32(2, true); else JEFI_FAST_F32(2, false);
+        if (fingerprint) JEFI_FAST_F32(2, true, 32); else JEFI_FAST_F32(2, false, 32);
       }
     } else {
       if (is_f64) {
-        if (fingerprint) JEFI_FAST(double, 1, true, 0); else JEFI_FAST(double, 1, false, 0);
+        if (fingerprint) JEFI_FAST(double, 1, true, 0, 32); else JEFI_FAST(double, 1, false, 0, 32);
       } else {
-        if (fingerprint) JEFI_FAST_F32(1, true); else JEFI_FAST_F32(1, false);
+        if (fingerprint) JEFI_FAST_F32(1, true, 32); else JEFI_FAST_F32(1, false, 32);
       }
     }
     return hipGetLastError();

@@ -232,6 +232,30 @@ def test_long_windows_take_the_chunked_path():
         assert np.array_equal(G.gpu_fingerprint(p, prec), fp_ref)
 
 
+@pytest.mark.parametrize("ratio", [4, 8, 10])
+def test_staging_window_sizes(ratio):
+    """Spacing / (c dt) = 4, 8, 10 with 8x8x8 tiles: slice windows of about
+    58, 114 and 142 slots, i.e. the 64- and 128-slot staging shapes and the
+    chunked kernel (FP64 stages at most 64 slots); fields and fingerprints
+    against the oracle, including points near the switch-on front."""
+    G = _gpu()
+    h = 0.1
+    src = centred_grid((10, 9, 11), h)
+    obs = Grid((9, 10, 8), tuple(src.origin[a] + (3, -2, 4)[a] * h for a in range(3)), (h, h, h))
+    dt = h / ratio
+    nt = 9 * ratio  # shorter than the longest separation: some pairs lie before the oldest slice
+    blobs = [Blob(1.0, 0.15, (0.0, 0.05, 0.0), (0.3, 0.0, 0.2)), Blob(-0.5, 0.1, (0.1, 0, 0), (0, 0.4, 0))]
+    hist = blob_history(src, blobs, nt, dt)
+    p = Problem(f"window{ratio}", src, obs, hist, dt, (nt - 1) * dt - 0.3 * dt, 0.0, nt - 1, 1.0,
+                workloads.default_screen(src))
+    Er, Br = oracle.eval_problem(p)
+    fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+    for prec in ["f64", "f32"]:
+        Eg, Bg = G.gpu_eval(p, prec)
+        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"window ratio {ratio} {prec}")
+        assert np.array_equal(G.gpu_fingerprint(p, prec), fp_ref)
+
+
 def test_exact_integer_boundaries_dump():
     """R/(c dt) exactly integral (d = 0.5, dt = 0.25): both device index
     paths return the canonical k, including on the slice boundary."""
