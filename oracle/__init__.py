@@ -24,6 +24,8 @@ _DEFAULT_LIB = os.path.join(_HERE, "libjefi_oracle.so")
 _LIB = _DEFAULT_LIB
 
 SCREENED = -(2 ** 31)
+STENCIL_SLOPE = 1  # time derivative = slope of the linear interpolant
+STENCIL_HOLD = 2   # history before the oldest slice = the oldest slice
 
 
 class _Grid(C.Structure):
@@ -71,7 +73,7 @@ def _load():
         P = C.POINTER
         lib.orc_eval.argtypes = [P(_Grid), P(_Grid), P(C.c_double), C.c_int32, C.c_double, C.c_double,
                                  C.c_double, C.c_double, C.c_int64, P(C.c_double), P(C.c_int64),
-                                 C.c_int64, P(C.c_double), P(C.c_double), C.c_int32]
+                                 C.c_int64, P(C.c_double), P(C.c_double), C.c_int32, C.c_int32]
         lib.orc_eval.restype = C.c_int
         lib.orc_slice_index_dump.argtypes = [P(_Grid), P(_Grid), C.c_int32, C.c_double, C.c_double,
                                              C.c_double, C.c_double, C.c_int64, P(C.c_double),
@@ -112,11 +114,15 @@ def _delta(src, screen):
 def eval_fields(src, obs, hist: np.ndarray, dt: float, t: float, t0: float = 0.0,
                 newest: Optional[int] = None, c: float = 1.0,
                 screen: Optional[Sequence[float]] = None, sel: Optional[Sequence[int]] = None,
-                threads: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+                threads: int = 0, stencil: int = 0) -> Tuple[np.ndarray, np.ndarray]:
     """E, B (FP64 [3][n_out]) at time t from ``hist[nt][4][n_src]``
     (oldest slice first; ``newest`` = absolute step of the last slice,
     default nt-1).  ``screen`` = half-widths (default half the source
-    spacing); ``sel`` = observation linear indices (default all)."""
+    spacing); ``sel`` = observation linear indices (default all).
+    ``stencil``: reading of the time stencil, bit 0 = derivative as the
+    slope of the interpolant (``STENCIL_SLOPE``), bit 1 = history before
+    the oldest slice held at its values (``STENCIL_HOLD``); 0 = the
+    interpolated backward difference and a zero past."""
     lib = _load()
     h = np.ascontiguousarray(hist, dtype=np.float64)
     nt = int(h.shape[0])
@@ -137,15 +143,17 @@ def eval_fields(src, obs, hist: np.ndarray, dt: float, t: float, t0: float = 0.0
     B = np.zeros((3, nout), dtype=np.float64)
     gs, go = _grid(src), _grid(obs)
     rc = lib.orc_eval(C.byref(gs), C.byref(go), _dptr(h), nt, float(dt), float(c), float(t),
-                      float(t0), int(newest), delta, sel_p, nout, _dptr(E), _dptr(B), int(threads))
+                      float(t0), int(newest), delta, sel_p, nout, _dptr(E), _dptr(B), int(threads),
+                      int(stencil))
     if rc != 0:
         raise ValueError(f"oracle rejected the problem (code {rc})")
     return E, B
 
 
-def eval_problem(p, sel=None, threads: int = 0):
+def eval_problem(p, sel=None, threads: int = 0, stencil: int = 0):
     """``eval_fields`` for a ``workloads.Problem``."""
-    return eval_fields(p.src, p.obs, p.hist, p.dt, p.t, p.t0, p.newest, p.c, p.screen, sel, threads)
+    return eval_fields(p.src, p.obs, p.hist, p.dt, p.t, p.t0, p.newest, p.c, p.screen, sel, threads,
+                       stencil)
 
 
 def slice_index_dump(src, obs, nt: int, dt: float, t: float, t0: float = 0.0,

@@ -24,6 +24,15 @@
  *     D_k = (h_k - h_(k-1))/dt;
  *   - slices before the oldest stored one are zero (the paper's sources
  *     vanish before t = 0), including h_(-1) inside D_0;
+ * Two alternative readings of those last two points are selectable through
+ * the `stencil` bits of orc_eval (the default, 0, is the reading above):
+ *   - bit 0: the time derivative is the slope of the linear interpolant on
+ *     the interval holding t_r, (h_(k+1) - h_k)/dt, instead of the
+ *     interpolated backward difference;
+ *   - bit 1: slices before the oldest stored one hold the oldest slice's
+ *     values (sources constant before the retained window), so h_(-1) = h_0
+ *     inside D_0 and no pair is ever wholly in an empty past.
+ * Neither changes the slice index k or the screening decision.
  *   - the slice index is k = a_i + floor(u), u = a_f - R*inv_cdt with the
  *     host split a = (t - t0)/dt - s_old = a_i + a_f, all in FP64 with no
  *     contraction; the interpolation weight is f = u - floor(u) and slice
@@ -142,9 +151,13 @@ static int orc_pair(const double ro[3], const double rs[3], const double delta[3
   return 0;
 }
 
-/* History value of channel ch at logical slice j (zero before slice 0). */
-static double orc_h(const double* hist, int64_t ns, int64_t j, int ch, int64_t s) {
-  if (j < 0) return 0.0;
+/* History value of channel ch at logical slice j.  Before slice 0 it is
+ * zero, or slice 0's value when `hold` is set. */
+static double orc_h(const double* hist, int64_t ns, int64_t j, int ch, int64_t s, int hold) {
+  if (j < 0) {
+    if (!hold) return 0.0;
+    j = 0;
+  }
   return hist[(j * 4 + ch) * ns + s];
 }
 
@@ -157,11 +170,15 @@ static double orc_h(const double* hist, int64_t ns, int64_t j, int ch, int64_t s
  *   E, B  : FP64 [3][n_out] with n_out = n_sel or n_obs, component-major
  *   delta : screening half-widths
  *   threads: OpenMP threads (0 = runtime default)
+ *   stencil: reading of the time stencil (bits in the header comment; 0 = default)
  * Returns 0, -1 (bad arguments) or -2 (t after the newest slice). */
 int orc_eval(const orc_grid* src, const orc_grid* obs, const double* hist, int32_t nt,
              double dt, double c, double t, double t0, int64_t newest, const double delta[3],
-             const int64_t* sel, int64_t n_sel, double* E, double* B, int32_t threads) {
+             const int64_t* sel, int64_t n_sel, double* E, double* B, int32_t threads,
+             int32_t stencil) {
   if (!src || !obs || !hist || !E || !B || !delta) return -1;
+  if (stencil < 0 || stencil > 3) return -1;
+  const int slope = (stencil & 1) != 0, hold = (stencil & 2) != 0;
   if (!orc_grid_ok(src) || !orc_grid_ok(obs)) return -1;
   orc_time tm;
   int rc = orc_time_prelude(t, t0, dt, newest, nt, c, &tm);
@@ -188,21 +205,23 @@ int orc_eval(const orc_grid* src, const orc_grid* obs, const double* hist, int32
       int64_t k;
       orc_centre(src, s, rs);
       if (orc_pair(ro, rs, delta, &tm, d, &R, &k, &f)) continue;
-      if (k < -1) continue; /* the whole stencil lies before the oldest slice */
-      if (f != 0.0 && k + 1 > (int64_t)nt - 1) { bad |= 2; continue; }
+      if (k < -1 && !hold) continue; /* the whole stencil lies before the oldest slice */
+      if ((f != 0.0 || slope) && k + 1 > (int64_t)nt - 1) { bad |= 2; continue; }
       double val[4], der[4];
       for (int ch = 0; ch < 4; ++ch) {
-        double h0 = orc_h(hist, ns, k, ch, s);
-        double hm = orc_h(hist, ns, k - 1, ch, s);
+        double h0 = orc_h(hist, ns, k, ch, s, hold);
+        double hm = orc_h(hist, ns, k - 1, ch, s, hold);
         double d0 = (h0 - hm) * inv_dt;
         double v = (1.0 - f) * h0;
         double w = (1.0 - f) * d0;
         if (f != 0.0) {
-          double h1 = orc_h(hist, ns, k + 1, ch, s);
+          double h1 = orc_h(hist, ns, k + 1, ch, s, hold);
           double d1 = (h1 - h0) * inv_dt;
           v += f * h1;
           w += f * d1;
         }
+        /* slope reading: the interpolant's derivative on [k, k+1], also at f == 0 */
+        if (slope) w = (orc_h(hist, ns, k + 1, ch, s, hold) - h0) * inv_dt;
         val[ch] = v;
         der[ch] = w;
       }

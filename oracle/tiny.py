@@ -8,6 +8,9 @@ it shares neither code nor summation scheme with the C oracle.  The same
 readings apply: linear interpolation in time between slices, backward
 differences interpolated the same way, zero history before the oldest slice,
 the slice index from the FP64 split a = a_i + a_f, and the cube screening.
+The two alternative time-stencil readings (derivative as the slope of the
+interpolant; history before the oldest slice held at its values) are
+selected by the same ``stencil`` bits as the C oracle.
 
 Cost is O(n_obs * n_src * 4) Python operations: keep n_obs * n_src <= ~3e5.
 """
@@ -58,9 +61,12 @@ def slice_decision(ro, rs, delta, ai, af, inv_cdt):
 
 
 def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
-                sel: Sequence[int] | None = None):
+                sel: Sequence[int] | None = None, stencil: int = 0):
     """E, B as lists [3][n_out] of floats.  ``hist[j][ch][s]`` with j = 0
-    the oldest of nt slices."""
+    the oldest of nt slices.  ``stencil`` bit 0: slope derivative; bit 1:
+    held past."""
+    slope = bool(stencil & 1)
+    hold = bool(stencil & 2)
     nt = len(hist)
     ai, af, inv_cdt = time_split(t, t0, dt, newest, nt, c)
     ns = src.n[0] * src.n[1] * src.n[2]
@@ -72,7 +78,9 @@ def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
     B = [[0.0] * len(idx) for _ in range(3)]
 
     def H(j, ch, s):
-        return 0.0 if j < 0 else float(hist[j][ch][s])
+        if j < 0:
+            return float(hist[0][ch][s]) if hold else 0.0
+        return float(hist[j][ch][s])
 
     for q, o in enumerate(idx):
         ro = _centre(obs, o)
@@ -83,7 +91,7 @@ def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
             if dec is None:
                 continue
             d, R, k, f = dec
-            if k < -1:
+            if k < -1 and not hold:
                 continue
             # value and backward difference at the retarded time, both as
             # linear interpolations between slices k and k+1
@@ -102,6 +110,11 @@ def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
                 else:
                     val.append(lo)
                     der.append(dlo)
+                if slope:
+                    # derivative of the piecewise-linear interpolant on [k, k+1]
+                    if k + 1 > nt - 1:
+                        raise ValueError("stencil reaches past the newest slice")
+                    der[-1] = (H(k + 1, ch, s) - lo) / dt
             rho, rhod = val[0], der[0]
             J, Jd = val[1:], der[1:]
             for a in range(3):

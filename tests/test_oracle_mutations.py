@@ -21,12 +21,17 @@ MUTATIONS = {
     "prefactor 1/(2 pi)": ("/ (4.0 * M_PI);", "/ (2.0 * M_PI);"),
     "rho_dot weighted by 1/R^3": ("d[a] * rhod * iR2", "d[a] * rhod * iR3"),
     "derivative of the interpolant": ("double d0 = (h0 - hm) * inv_dt;",
-                                      "double d0 = (orc_h(hist, ns, k + 1, ch, s) - h0) * inv_dt;"),
+                                      "double d0 = (orc_h(hist, ns, k + 1, ch, s, hold) - h0) * inv_dt;"),
     "slice index one late": ("*k = tm->a_i + (int64_t)m;", "*k = tm->a_i + (int64_t)m + 1;"),
     "weight f complemented": ("*f = u - m;", "*f = 1.0 - (u - m);"),
-    "past held at the oldest slice": ("if (j < 0) return 0.0;", "if (j < 0) j = 0;"),
+    "past held at the oldest slice": ("if (!hold) return 0.0;", "if (0) return 0.0;"),
     "retarded time uses R*c*dt": ("out->inv_cdt = 1.0 / (c * dt);", "out->inv_cdt = c / dt;"),
     "Jdot missing from B": ("-(cJ[a] * iR3 + cD[a] * iR2)", "-(cJ[a] * iR3)"),
+    "slope reading uses the backward difference": ("if (slope) w = (orc_h(hist, ns, k + 1, ch, s, hold) - h0) * inv_dt;",
+                                                   "if (slope) w = (h0 - hm) * inv_dt;"),
+    "held past still culls old stencils": ("if (k < -1 && !hold) continue;", "if (k < -1) continue;"),
+    "held past keeps h(-1) = 0 in D_0": ("double hm = orc_h(hist, ns, k - 1, ch, s, hold);",
+                                         "double hm = k - 1 < 0 ? 0.0 : orc_h(hist, ns, k - 1, ch, s, hold);"),
 }
 
 PIN_CALLS = [
@@ -39,6 +44,11 @@ PIN_CALLS = [
     pins.test_current_ring_on_axis,
     pins.test_exact_integer_retarded_positions,
     pins.test_saturation_for_constant_sources,
+    pins.test_quadratic_history_slope_reading,
+    lambda: pins.test_switch_on_slope_reading("k=-1"),
+    lambda: pins.test_held_past_constant_history_is_static_at_any_time(2),
+    lambda: pins.test_held_past_linear_history(2),
+    lambda: pins.test_held_past_linear_history(3),
 ]
 
 

@@ -171,6 +171,117 @@ def test_switch_on_at_the_oldest_slice(where):
     assert np.all(B == 0.0)
 
 
+def test_quadratic_history_slope_reading():
+    """The slope reading (stencil bit 0) on rho = beta t^2: the value is the
+    same interpolant, the derivative is the slope of the interpolant on the
+    interval holding t_r, beta (t_(k+1)^2 - t_k^2)/dt = beta (2 t_r + (1 - 2f) dt)."""
+    src = _single_cell()
+    obs = _obs_points(n=(4, 3, 3), origin=(0.55, 0.1, -0.2), sp=(0.13, 0.11, 0.07))
+    beta, dt = 0.6, 0.05
+    nt = 100
+    hist = _hist_from(lambda t: [beta * t * t, 0.0, 0.0, 0.0], nt, 0, dt)
+    t = (nt - 1) * dt
+    E, _ = oracle.eval_fields(src, obs, hist, dt, t=t, screen=(0, 0, 0), stencil=oracle.STENCIL_SLOPE)
+    d = _centres(obs)
+    R = np.linalg.norm(d, axis=1)
+    tr = t - R
+    pos = tr / dt
+    f = pos - np.floor(pos)
+    val = beta * (tr ** 2 + f * (1 - f) * dt ** 2)
+    der = beta * (2 * tr + (1 - 2 * f) * dt)
+    dom = 0.1 * 0.2 * 0.15
+    E_ref = (dom / FOUR_PI) * (d.T * val / R ** 3 + d.T * der / R ** 2)
+    assert np.allclose(E, E_ref, rtol=1e-10, atol=1e-15)
+
+
+@pytest.mark.parametrize("where", ["k=-1", "k=0", "dead"])
+def test_switch_on_slope_reading(where):
+    """Constant rho = h from the oldest slice on, zero before it, slope
+    reading: k = -1 -> value f h, derivative h/dt (the whole jump over one
+    interval); k = 0 -> value h, derivative 0; wholly before -> 0."""
+    h, dt = 2.5, 0.1
+    nt = 6
+    src = _single_cell(h=(0.1, 0.1, 0.1))
+    t = (nt - 1) * dt
+    target = {"k=-1": -0.037, "k=0": 0.063, "dead": -0.13}[where]
+    R = t - target
+    obs = Grid((1, 1, 1), (R * 0.6, R * 0.8, 0.0), (0.1, 0.1, 0.1))
+    hist = _hist_from(lambda tt: [h, 0.0, 0.0, 0.0], nt, 0, dt)
+    E, B = oracle.eval_fields(src, obs, hist, dt, t=t, screen=(0, 0, 0), stencil=oracle.STENCIL_SLOPE)
+    d = _centres(obs)[0]
+    Rr = float(np.linalg.norm(d))
+    pos = (t - Rr) / dt
+    f = pos - math.floor(pos)
+    if where == "dead":
+        assert np.all(E == 0.0) and np.all(B == 0.0)
+        return
+    val, der = (f * h, h / dt) if where == "k=-1" else (h, 0.0)
+    E_ref = (1e-3 / FOUR_PI) * (d * val / Rr ** 3 + d * der / Rr ** 2)
+    assert np.allclose(E[:, 0], E_ref, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("stencil", [2, 3])
+def test_held_past_constant_history_is_static_at_any_time(stencil):
+    """History held at the oldest slice (stencil bit 1) and constant sources:
+    the retarded sources are the constant ones at every t_r, so E and B are
+    the static Coulomb and Biot-Savart fields at every evaluation time,
+    including times long before the oldest slice, where the zero past gives
+    exactly nothing."""
+    src = _single_cell()
+    obs = _obs_points()
+    q, J = 0.8, np.array([0.3, -1.1, 0.6])
+    dt, nt = 0.05, 4
+    hist = _hist_from(lambda t: [q, *J], nt, 0, dt)
+    d = _centres(obs)
+    R = np.linalg.norm(d, axis=1)
+    dom = 0.1 * 0.2 * 0.15
+    E_ref = (q * dom / FOUR_PI) * d.T / R ** 3
+    B_ref = (dom / FOUR_PI) * np.cross(J[None, :], d).T / R ** 3
+    for t in [(nt - 1) * dt, 0.0, -0.4, -7.0]:
+        E, B = oracle.eval_fields(src, obs, hist, dt, t=t, screen=(0, 0, 0), stencil=stencil)
+        assert np.allclose(E, E_ref, rtol=1e-14, atol=0), t
+        assert np.allclose(B, B_ref, rtol=1e-14, atol=1e-18), t
+    E0, B0 = oracle.eval_fields(src, obs, hist, dt, t=-7.0, screen=(0, 0, 0))
+    assert np.all(E0 == 0.0) and np.all(B0 == 0.0)
+
+
+@pytest.mark.parametrize("stencil", [2, 3])
+def test_held_past_linear_history(stencil):
+    """rho = a + b t from the oldest slice t_old on, held at a + b t_old
+    before it.  Value: a + b max(t_r, t_old) (the interpolant between two
+    held slices is flat).  Derivative: 0 while t_r < t_old; on the first
+    interval [t_old, t_old + dt) the interpolated backward difference gives
+    f b (D_0 = 0 since h_(-1) = h_0) and the slope reading gives b; b later."""
+    a, b = 0.7, -1.3
+    dt, nt, s_old = 0.05, 8, 3
+    t_old = s_old * dt
+    newest = s_old + nt - 1
+    t = newest * dt
+    hist = _hist_from(lambda tt: [a + b * tt, 0.0, 0.0, 0.0], nt, s_old, dt)
+    src = _single_cell(h=(0.1, 0.1, 0.1))
+    # retarded times spread over the held past, the first interval and later
+    Rs = t - (t_old + np.array([-0.31, -0.12, -0.037, 0.011, 0.029, 0.047, 0.09, 0.2]))
+    E = np.zeros((3, len(Rs)))
+    for i, R in enumerate(Rs):
+        g = Grid((1, 1, 1), (R * 0.36, R * 0.48, R * 0.8), (0.1, 0.1, 0.1))
+        e, _ = oracle.eval_fields(src, g, hist, dt, t=t, newest=newest, screen=(0, 0, 0), stencil=stencil)
+        E[:, i] = e[:, 0]
+    d = np.stack([Rs * 0.36, Rs * 0.48, Rs * 0.8])
+    Rr = np.linalg.norm(d, axis=0)
+    tr = t - Rr
+    pos = (tr - t_old) / dt
+    f = pos - np.floor(pos)
+    val = a + b * np.maximum(tr, t_old)
+    first = (tr >= t_old) & (tr < t_old + dt)
+    if stencil & 1:
+        der = np.where(tr >= t_old, b, 0.0)
+    else:
+        der = np.where(tr >= t_old + dt, b, np.where(first, f * b, 0.0))
+    assert first.sum() == 3 and (tr < t_old).sum() == 3
+    E_ref = (1e-3 / FOUR_PI) * (d * val / Rr ** 3 + d * der / Rr ** 2)
+    assert np.allclose(E, E_ref, rtol=1e-11, atol=0)
+
+
 def _sphere_quadrature(n_theta=24, n_phi=48):
     x, w = np.polynomial.legendre.leggauss(n_theta)
     phi = (np.arange(n_phi) + 0.5) * (2 * math.pi / n_phi)
@@ -319,6 +430,20 @@ def test_c_oracle_matches_pure_python_on_random_tiny_problems(seed):
     d1 = oracle.slice_index_dump(src, obs, nt, dt, t, t0, newest, c, screen)
     d2 = np.array(tiny.slice_index_dump(src, obs, nt, dt, t, t0, newest, c, screen))
     assert np.array_equal(d1, d2)
+
+
+@pytest.mark.parametrize("seed,stencil", [(s, st) for s in range(4) for st in (1, 2, 3)])
+def test_c_oracle_matches_pure_python_stencil_readings(seed, stencil):
+    rng = np.random.default_rng(300 + seed)
+    src, obs, hist, dt, t, t0, newest, c, screen = _random_problem(rng)
+    if seed % 2:
+        t -= 0.5  # many stencils in the past
+    E, B = oracle.eval_fields(src, obs, hist, dt, t, t0, newest, c, screen, stencil=stencil)
+    E2, B2 = tiny.eval_fields(src, obs, hist, dt, t, t0, newest, c, screen, stencil=stencil)
+    E2, B2 = np.array(E2), np.array(B2)
+    scale = max(np.abs(E2).max(), np.abs(B2).max(), 1e-300)
+    assert np.abs(E - E2).max() <= 1e-13 * scale
+    assert np.abs(B - B2).max() <= 1e-13 * scale
 
 
 def test_exact_integer_retarded_positions():
