@@ -70,7 +70,7 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_path(p, extra, prec, steps, warmup):
+def run_path(p, extra, prec, steps, warmup, flags=0):
     """Time `steps` steps (push + eval) after `warmup`; returns a dict."""
     import torch
     import paper_2104_05426_amd as J
@@ -78,6 +78,7 @@ def run_path(p, extra, prec, steps, warmup):
     tdt = torch.float64 if prec == "f64" else torch.float32
     opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP,
                                  c=p.c, screen=p.screen)
+    opt.flags = flags
     store, h = J.upload_history(p.src, p.hist, hdt, t0=p.t0, newest=p.newest, capacity=p.nt)
     slices = [torch.as_tensor(extra[i], dtype=tdt).cuda().contiguous() for i in range(extra.shape[0])]
     n_obs = p.obs.size
@@ -402,6 +403,38 @@ def run_serve_workload(args):
     }
 
 
+def run_stencil_variants(args, p, extra):
+    """The same workload under the alternative time-stencil readings (FP32
+    path): derivative as the slope of the interpolant, history before the
+    oldest slice held at its values (no pair culled as past), both; rate and
+    parity against the oracle with the same reading on sampled points."""
+    import oracle
+    import paper_2104_05426_amd as J
+    from oracle.compare import max_rel_l2
+    K, W = 5, 2
+    pairs = p.src.size * p.obs.size
+    full = np.concatenate([p.hist, extra], axis=0)
+    sel = np.sort(np.random.default_rng(13).choice(p.obs.size, size=8, replace=False))
+    out = {}
+    for name, flag, st in [("slope", J.JEFI_FLAG_DERIV_SLOPE, oracle.STENCIL_SLOPE),
+                           ("hold", J.JEFI_FLAG_PAST_HOLD, oracle.STENCIL_HOLD),
+                           ("slope+hold", J.JEFI_FLAG_DERIV_SLOPE | J.JEFI_FLAG_PAST_HOLD,
+                            oracle.STENCIL_SLOPE | oracle.STENCIL_HOLD)]:
+        r = run_path(p, extra, "f32", K, W, flags=flag)
+        last = r["newest"]
+        win = full[last - p.nt + 1:last + 1]
+        Er, Br = oracle.eval_fields(p.src, p.obs, win, p.dt, p.t0 + last * p.dt, p.t0, last, p.c, p.screen,
+                                    sel=sel, stencil=st)
+        err = max_rel_l2(r["E"][:, sel], r["B"][:, sel], Er, Br)
+        v = pairs * K / r["wall_s"] / 1e9
+        log(f"stencil {name}: {v:.1f} G pairs/s, eval {np.mean(r['eval_ms']):.2f} ms, parity {err:.2e}")
+        out[name] = {"value": round(v, 3), "unit": "G pairs/s", "steps": K,
+                     "eval_ms_mean": round(float(np.mean(r["eval_ms"])), 3),
+                     "parity": {"sampled_points": int(len(sel)), "max_rel_l2_f32": float(f"{err:.3e}"),
+                                "ok": bool(err <= 1e-5)}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,6 +447,8 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-companion", action="store_true",
                     help="skip the 32^3 single-instance line reported beside the 64^3 headline")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the time-stencil variants of the headline workload")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the request stream for --workload serve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -451,7 +486,7 @@ def main():
     p = make_workload(args.workload)
     K, W = args.steps, args.warmup
     K64 = args.fp64_steps if args.fp64_steps is not None else max(2, K // 2)
-    n_extra = W + max(K, K64)
+    n_extra = max(W + max(K, K64), 7)  # the stencil variants run 2 + 5 steps
     log(f"workload {p.name}: {p.src.size} src x {p.obs.size} obs, nt {p.nt}; {n_extra} extra slices")
     extra = workloads.blob_history(p.src, p.blobs, list(range(p.newest + 1, p.newest + 1 + n_extra)), p.dt,
                                    p.t0)
@@ -505,6 +540,8 @@ def main():
 
     if args.workload == "large" and not args.no_companion:
         res["single_instance_32^3"] = run_companion(args)
+    if args.workload == "large" and not args.no_variants:
+        res["stencil_variants"] = run_stencil_variants(args, p, extra)
 
     if not args.no_parity or not args.no_cpu_baseline:
         import oracle

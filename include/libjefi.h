@@ -107,7 +107,8 @@ typedef struct {
   double screen[3];      /* screening half-widths, used when screen_set != 0 */
   int32_t screen_set;    /* 0: half the source spacing per axis (default) */
   int32_t precision;     /* jefi_precision (default JEFI_PREC_F32_COMP) */
-  uint32_t flags;        /* 0 or one JEFI_FLAG_INDEX_* value; other bits are rejected */
+  uint32_t flags;        /* at most one JEFI_FLAG_INDEX_* value, plus JEFI_FLAG_DERIV_SLOPE
+                            and/or JEFI_FLAG_PAST_HOLD; other bits are rejected (EINVAL) */
   int32_t tile_config;   /* launch shape: 0 = automatic (autotuned table, else a size
                             heuristic), 1 = 8x8x8 observation tiles (512 threads),
                             2 = 8x8x4 tiles (256 threads) */
@@ -121,6 +122,29 @@ typedef struct {
 enum {
   JEFI_FLAG_INDEX_GUARD = 1, /* decide in FP32, redo in FP64 only inside the guard band */
   JEFI_FLAG_INDEX_TABLE = 2  /* decide every pair by its FP64 r2 against a threshold table */
+};
+
+/* Readings of the time stencil.  The paper takes time derivatives as the
+ * backward difference over one step and its sources vanish before they are
+ * switched on (section "GPU implementation of Jefimenko's equations" and the
+ * source definitions of the constant and sinusoidal tests); between slices
+ * the library interpolates linearly.  By default the derivative at t_r is
+ * therefore the linear interpolation of the slice-wise backward differences
+ * (h_k - h_(k-1))/dt, and the history is zero before the oldest slice of the
+ * window (pairs whose stencil lies wholly before it contribute nothing).
+ * These flags select the alternatives, in any combination with each other
+ * and with an index flag:
+ *   JEFI_FLAG_DERIV_SLOPE: the derivative is the slope of the linear
+ *     interpolant on the interval that holds t_r, (h_(k+1) - h_k)/dt.
+ *   JEFI_FLAG_PAST_HOLD: before the oldest slice of the window the history
+ *     holds that slice's values (sources constant before the window); no
+ *     pair is then culled as lying in the past, so every unscreened pair is
+ *     computed.
+ * Neither changes the slice index k, the screening decision or the
+ * fingerprint (jefi_slice_fingerprint, jefi_slice_index_dump). */
+enum {
+  JEFI_FLAG_DERIV_SLOPE = 4,
+  JEFI_FLAG_PAST_HOLD = 8
 };
 
 const char* jefi_version(void);

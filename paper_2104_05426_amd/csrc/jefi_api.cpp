@@ -131,8 +131,14 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
     return fail(JEFI_EINVAL, "unknown precision %d", opt->precision);
   if (opt->tile_config < 0 || opt->tile_config > 2)
     return fail(JEFI_EINVAL, "tile_config %d (0 = auto, 1 = 8x8x8, 2 = 8x8x4)", opt->tile_config);
-  if (opt->flags != 0 && opt->flags != JEFI_FLAG_INDEX_GUARD && opt->flags != JEFI_FLAG_INDEX_TABLE)
-    return fail(JEFI_EINVAL, "flags 0x%x (0, JEFI_FLAG_INDEX_GUARD or JEFI_FLAG_INDEX_TABLE)", opt->flags);
+  const unsigned known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE |
+                         JEFI_FLAG_PAST_HOLD;
+  const unsigned idx = opt->flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE);
+  if ((opt->flags & ~known) != 0 || idx == (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE))
+    return fail(JEFI_EINVAL,
+                "flags 0x%x (at most one JEFI_FLAG_INDEX_* value, plus JEFI_FLAG_DERIV_SLOPE and/or "
+                "JEFI_FLAG_PAST_HOLD)",
+                opt->flags);
   r->flags = opt->flags;
   r->c = opt->c;
   r->precision = opt->precision;
@@ -278,13 +284,18 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   std::memset(&p, 0, sizeof p);
   plan->multi = 0;
   plan->wsel = 32;
-  plan->all_dead = ts.a_i <= -2;  // every pair's stencil lies before the oldest slice
+  // every pair's stencil lies before the oldest slice: zero fields, unless
+  // the past is held (then every pair reads slice 0 through slot -2, and
+  // a_i = -2 places them all there)
+  const bool hold = (r.flags & JEFI_FLAG_PAST_HOLD) != 0;
+  plan->all_dead = !hold && ts.a_i <= -2;
   p.src = to_gd(src);
   p.obs = to_gd(obs);
   p.n_bricks = (int)brick_count(src, &p.nbx, &p.nby, &p.nbz);
   set_tiles(p, obs, tile_z);
   plan->empty = p.n_tiles == 0 || p.n_bricks == 0;
-  p.a_i = plan->all_dead ? -2 : (int)ts.a_i;
+  p.a_i = ts.a_i <= -2 ? -2 : (int)ts.a_i;
+  p.stencil = ((r.flags & JEFI_FLAG_DERIV_SLOPE) ? kStencilSlope : 0) | (hold ? kStencilHold : 0);
   p.a_f = ts.a_f;
   p.inv_cdt = ts.inv_cdt;
   p.inv_dt = 1.0 / dt;
@@ -355,8 +366,9 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   // coordinate error on some axis: every FP32 separation there is nonzero.
   p.near_slack = std::max(1e-12, 4.0 * e_coord);
   p.exact_idx = 0;
-  if (p.use_thr && r.flags != JEFI_FLAG_INDEX_GUARD)
-    p.exact_idx = r.flags == JEFI_FLAG_INDEX_TABLE || guard_pairs_common(src, obs, ts, g) ? 1 : 0;
+  const unsigned idx_mode = r.flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE);
+  if (p.use_thr && idx_mode != JEFI_FLAG_INDEX_GUARD)
+    p.exact_idx = idx_mode == JEFI_FLAG_INDEX_TABLE || guard_pairs_common(src, obs, ts, g) ? 1 : 0;
   // Longest slice window any brick can need (the 8x8x8 tile bounds both shapes).
   const double wb = std::floor((diam_t + diam_b) * ts.inv_cdt * (1.0 + 1e-12) + 2.0 * p.margin + 1e-6) + 3.0;
   // Staging shape: 32 slots per cell, else 64 or 128 with fewer bricks per

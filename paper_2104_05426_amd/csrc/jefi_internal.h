@@ -24,6 +24,11 @@ struct GridD {
 };
 
 // Everything a pair-kernel launch needs; passed by value.
+// Time-stencil readings (pair kernels): derivative as the slope of the
+// linear interpolant; history before the oldest slice held at its values.
+constexpr int kStencilSlope = 1;
+constexpr int kStencilHold = 2;
+
 struct PairParams {
   GridD src, obs;
   int nbx, nby, nbz;
@@ -62,6 +67,8 @@ struct PairParams {
   double pref;           // dOmega / (4 pi)
   unsigned long long* fp;  // fingerprint output [n_obs][4]
   int direct;            // 1: one split, the pair kernel writes E/B itself
+  int stencil;           // kStencilSlope | kStencilHold, or 0 (interpolated backward
+                         // differences, zero history before the oldest slice)
 };
 
 struct EpilogueParams {

@@ -135,9 +135,11 @@ __device__ __forceinline__ void two_sum_acc(float& s, float& c, float x) {
   c += e;
 }
 
-// Four channels of one cell at logical slice j (zero outside 0..nt-1).
+// Four channels of one cell at logical slice j: zero after slice nt-1, and
+// before slice 0 zero or (held past) slice 0's values.
 template <class PP>
 __device__ __forceinline__ float4 ring4(const float* ring, const PP& p, int j, int b, int c) {
+  if (j < 0 && (p.stencil & kStencilHold)) j = 0;  // held past: slice 0 extends backwards
   if (j < 0 || j > p.nt - 1) return make_float4(0.f, 0.f, 0.f, 0.f);
   int slot = p.slot_base + j;
   if (slot >= p.capacity) slot -= p.capacity;
@@ -147,6 +149,7 @@ __device__ __forceinline__ float4 ring4(const float* ring, const PP& p, int j, i
 template <class PP>
 __device__ __forceinline__ void ring4(const double* ring, const PP& p, int j, int b, int c,
                                       double out[4]) {
+  if (j < 0 && (p.stencil & kStencilHold)) j = 0;
   if (j < 0 || j > p.nt - 1) {
     out[0] = out[1] = out[2] = out[3] = 0.0;
     return;
@@ -157,6 +160,110 @@ __device__ __forceinline__ void ring4(const double* ring, const PP& p, int j, in
       (const double2*)(ring + (long long)slot * p.slot_elems + ((long long)b * kBrickCells + c) * 4);
   const double2 lo = q[0], hi = q[1];
   out[0] = lo.x; out[1] = lo.y; out[2] = hi.x; out[3] = hi.y;
+}
+
+// ---- staging helpers: raw slices to (h, S, D, T) entries ----
+
+struct D4 {
+  double x, y, z, w;
+};
+
+template <class PP>
+__device__ __forceinline__ void load_raw(const float* ring, const PP& p, int jj, int b, int c,
+                                         float4& out) {
+  out = ring4(ring, p, jj, b, c);
+}
+
+template <class PP>
+__device__ __forceinline__ void load_raw(const double* ring, const PP& p, int jj, int b, int c,
+                                         D4& out) {
+  double v[4];
+  ring4(ring, p, jj, b, c, v);
+  out = D4{v[0], v[1], v[2], v[3]};
+}
+
+// Raw buffer resource word 3 for gfx9-family targets (32-bit data, no
+// swizzle); offsets at or beyond the resource's byte count read as zero.
+constexpr int kRawBufferFlags = 0x00020000;
+constexpr int kOutOfRange = 0x7ffffff0;  // above any ring the buffer path takes
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, int off, float4& out) {
+  const f32x4_t v = __builtin_bit_cast(f32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  out = make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, int off, D4& out) {
+  const f64x2_t lo = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+  const f64x2_t hi = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 16, 0));
+  out = D4{lo.x, lo.y, hi.x, hi.y};
+}
+
+__device__ __forceinline__ void zero_raw(float4& v) { v = make_float4(0.f, 0.f, 0.f, 0.f); }
+__device__ __forceinline__ void zero_raw(D4& v) { v = D4{0.0, 0.0, 0.0, 0.0}; }
+
+template <typename T>
+struct RawOf;
+template <>
+struct RawOf<float> {
+  using type = float4;
+};
+template <>
+struct RawOf<double> {
+  using type = D4;
+};
+
+// Entry (h, S, D, T) of slot k from raw slices k-1, k, k+1, written to the
+// planes: value h_k + f S, derivative D + f T.  Backward differences (the
+// default): D = (h_k - h_(k-1))/dt, T = D_(k+1) - D_k.  Slope of the
+// interpolant (SLOPE): D = (h_(k+1) - h_k)/dt, T = 0.
+template <bool SLOPE>
+__device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const float4& hm, const float4& h0,
+                                          const float4& h1, float inv_dt) {
+  float4 S, D, Tn;
+  S.x = h1.x - h0.x; S.y = h1.y - h0.y; S.z = h1.z - h0.z; S.w = h1.w - h0.w;
+  if (SLOPE) {
+    D.x = S.x * inv_dt; D.y = S.y * inv_dt; D.z = S.z * inv_dt; D.w = S.w * inv_dt;
+    Tn = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    D.x = (h0.x - hm.x) * inv_dt; D.y = (h0.y - hm.y) * inv_dt;
+    D.z = (h0.z - hm.z) * inv_dt; D.w = (h0.w - hm.w) * inv_dt;
+    Tn.x = S.x * inv_dt - D.x; Tn.y = S.y * inv_dt - D.y;
+    Tn.z = S.z * inv_dt - D.z; Tn.w = S.w * inv_dt - D.w;
+  }
+  lds[idx] = h0;
+  lds[PU + idx] = S;
+  lds[2 * PU + idx] = D;
+  lds[3 * PU + idx] = Tn;
+}
+
+template <bool SLOPE>
+__device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const D4& hm, const D4& h0,
+                                          const D4& h1, double inv_dt) {
+  const double a[4] = {hm.x, hm.y, hm.z, hm.w};
+  const double b[4] = {h0.x, h0.y, h0.z, h0.w};
+  const double c[4] = {h1.x, h1.y, h1.z, h1.w};
+  double S[4], D[4], Tn[4];
+  for (int q = 0; q < 4; ++q) {
+    S[q] = c[q] - b[q];
+    if (SLOPE) {
+      D[q] = S[q] * inv_dt;
+      Tn[q] = 0.0;
+    } else {
+      D[q] = (b[q] - a[q]) * inv_dt;
+      Tn[q] = S[q] * inv_dt - D[q];
+    }
+  }
+  double2* l2 = (double2*)lds;
+  l2[idx] = make_double2(b[0], b[1]);
+  l2[PU + idx] = make_double2(b[2], b[3]);
+  l2[2 * PU + idx] = make_double2(S[0], S[1]);
+  l2[3 * PU + idx] = make_double2(S[2], S[3]);
+  l2[4 * PU + idx] = make_double2(D[0], D[1]);
+  l2[5 * PU + idx] = make_double2(D[2], D[3]);
+  l2[6 * PU + idx] = make_double2(Tn[0], Tn[1]);
+  l2[7 * PU + idx] = make_double2(Tn[2], Tn[3]);
 }
 
 // Geometry of one observation tile: first/last point indices, the FP64
@@ -193,7 +300,8 @@ __device__ __forceinline__ TileGeom tile_geom(const PP& p, int tile) {
 // the rounded canonical values too).  ti = (wlo, whi, flags, b) with flags
 // bit0 = dead (whole window before the oldest slice), bit1 = near (some pair
 // may be screened), bit2 = some pair lies before slot -2 (its floor position
-// must be clamped to the window's zero entry), bits 8..15 = valid cells;
+// must be clamped to the window's slot -2 entry: zero, or the held slice 0
+// with zero derivative), bits 8..15 = valid cells;
 // tf = brick corner relative to
 // the tile reference in FP32; cc = canonical x0, x1, y0, y1, z0, z1.
 template <class PP>
@@ -237,7 +345,11 @@ __device__ __forceinline__ void brick_info(const PP& p, const TileGeom& g, int b
   const int jlo = p.a_i + (int)__builtin_fmax(__builtin_floor(ulo), -1e9);
   int jhi = p.a_i + (int)__builtin_fmax(__builtin_floor(uhi), -1e9);
   jhi = min(jhi, p.nt - 1);
-  const bool dead = jhi < -1;
+  // held past: a window wholly before slice -1 still reads the held values
+  // through its clamp entry, so no brick is dead
+  const bool hold = (p.stencil & kStencilHold) != 0;
+  if (hold) jhi = max(jhi, -2);
+  const bool dead = !hold && jhi < -1;
   // cells with cx = 1 (cy = 1, cz = 1) exist when the brick has two layers in x (y, z)
   const int vmask = (i1 > i0 ? 0xff : 0x55) & (j1 > j0 ? 0xff : 0x33) & (k1 > k0 ? 0xff : 0x0f);
   ti = make_int4(max(jlo, -2), jhi, (dead ? 1 : 0) | (near ? 2 : 0) | (jlo < -2 ? 4 : 0) | (vmask << 8), b);
@@ -324,40 +436,14 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
         const int k = ti.x + cs + kk;
         if (k > ti.y) continue;
         const int e = (j * kBrickCells + c) * kWmax + kk;
-        if constexpr (sizeof(T) == 4) {
-          const float4 hm = ring4(ring, p, k - 1, ti.w, c);
-          const float4 h0 = ring4(ring, p, k, ti.w, c);
-          const float4 h1 = ring4(ring, p, k + 1, ti.w, c);
-          float4 S, D, Tn;
-          S.x = h1.x - h0.x; S.y = h1.y - h0.y; S.z = h1.z - h0.z; S.w = h1.w - h0.w;
-          D.x = (h0.x - hm.x) * inv_dt; D.y = (h0.y - hm.y) * inv_dt;
-          D.z = (h0.z - hm.z) * inv_dt; D.w = (h0.w - hm.w) * inv_dt;
-          Tn.x = S.x * inv_dt - D.x; Tn.y = S.y * inv_dt - D.y;
-          Tn.z = S.z * inv_dt - D.z; Tn.w = S.w * inv_dt - D.w;
-          lds[e] = h0;
-          lds[PU + e] = S;
-          lds[2 * PU + e] = D;
-          lds[3 * PU + e] = Tn;
-        } else {
-          double hm[4], h0[4], h1[4], S[4], D[4], Tn[4];
-          ring4(ring, p, k - 1, ti.w, c, hm);
-          ring4(ring, p, k, ti.w, c, h0);
-          ring4(ring, p, k + 1, ti.w, c, h1);
-          for (int q = 0; q < 4; ++q) {
-            S[q] = h1[q] - h0[q];
-            D[q] = (h0[q] - hm[q]) * inv_dt;
-            Tn[q] = S[q] * inv_dt - D[q];
-          }
-          double2* l2 = (double2*)lds;
-          l2[e] = make_double2(h0[0], h0[1]);
-          l2[PU + e] = make_double2(h0[2], h0[3]);
-          l2[2 * PU + e] = make_double2(S[0], S[1]);
-          l2[3 * PU + e] = make_double2(S[2], S[3]);
-          l2[4 * PU + e] = make_double2(D[0], D[1]);
-          l2[5 * PU + e] = make_double2(D[2], D[3]);
-          l2[6 * PU + e] = make_double2(Tn[0], Tn[1]);
-          l2[7 * PU + e] = make_double2(Tn[2], Tn[3]);
-        }
+        typename RawOf<T>::type hm, h0, h1;
+        load_raw(ring, p, k - 1, ti.w, c, hm);
+        load_raw(ring, p, k, ti.w, c, h0);
+        load_raw(ring, p, k + 1, ti.w, c, h1);
+        if (p.stencil & kStencilSlope)
+          put_entry<true>(lds, PU, e, hm, h0, h1, inv_dt);
+        else
+          put_entry<false>(lds, PU, e, hm, h0, h1, inv_dt);
       }
       __syncthreads();
 
@@ -575,93 +661,6 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
 // 8 cells first (one divergent FP64 fix-up if any falls in the guard band),
 // then branch-free LDS reads and field arithmetic.
 
-struct D4 {
-  double x, y, z, w;
-};
-
-template <class PP>
-__device__ __forceinline__ void load_raw(const float* ring, const PP& p, int jj, int b, int c,
-                                         float4& out) {
-  out = ring4(ring, p, jj, b, c);
-}
-
-template <class PP>
-__device__ __forceinline__ void load_raw(const double* ring, const PP& p, int jj, int b, int c,
-                                         D4& out) {
-  double v[4];
-  ring4(ring, p, jj, b, c, v);
-  out = D4{v[0], v[1], v[2], v[3]};
-}
-
-// Raw buffer resource word 3 for gfx9-family targets (32-bit data, no
-// swizzle); offsets at or beyond the resource's byte count read as zero.
-constexpr int kRawBufferFlags = 0x00020000;
-constexpr int kOutOfRange = 0x7ffffff0;  // above any ring the buffer path takes
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-typedef double f64x2_t __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, int off, float4& out) {
-  const f32x4_t v = __builtin_bit_cast(f32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-  out = make_float4(v.x, v.y, v.z, v.w);
-}
-
-__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, int off, D4& out) {
-  const f64x2_t lo = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-  const f64x2_t hi = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 16, 0));
-  out = D4{lo.x, lo.y, hi.x, hi.y};
-}
-
-__device__ __forceinline__ void zero_raw(float4& v) { v = make_float4(0.f, 0.f, 0.f, 0.f); }
-__device__ __forceinline__ void zero_raw(D4& v) { v = D4{0.0, 0.0, 0.0, 0.0}; }
-
-template <typename T>
-struct RawOf;
-template <>
-struct RawOf<float> {
-  using type = float4;
-};
-template <>
-struct RawOf<double> {
-  using type = D4;
-};
-
-// Entry (h, S, D, T) of slot k from raw slices k-1, k, k+1, written to the planes.
-__device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const float4& hm, const float4& h0,
-                                          const float4& h1, float inv_dt) {
-  float4 S, D, Tn;
-  S.x = h1.x - h0.x; S.y = h1.y - h0.y; S.z = h1.z - h0.z; S.w = h1.w - h0.w;
-  D.x = (h0.x - hm.x) * inv_dt; D.y = (h0.y - hm.y) * inv_dt;
-  D.z = (h0.z - hm.z) * inv_dt; D.w = (h0.w - hm.w) * inv_dt;
-  Tn.x = S.x * inv_dt - D.x; Tn.y = S.y * inv_dt - D.y;
-  Tn.z = S.z * inv_dt - D.z; Tn.w = S.w * inv_dt - D.w;
-  lds[idx] = h0;
-  lds[PU + idx] = S;
-  lds[2 * PU + idx] = D;
-  lds[3 * PU + idx] = Tn;
-}
-
-__device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const D4& hm, const D4& h0,
-                                          const D4& h1, double inv_dt) {
-  const double a[4] = {hm.x, hm.y, hm.z, hm.w};
-  const double b[4] = {h0.x, h0.y, h0.z, h0.w};
-  const double c[4] = {h1.x, h1.y, h1.z, h1.w};
-  double S[4], D[4], Tn[4];
-  for (int q = 0; q < 4; ++q) {
-    S[q] = c[q] - b[q];
-    D[q] = (b[q] - a[q]) * inv_dt;
-    Tn[q] = S[q] * inv_dt - D[q];
-  }
-  double2* l2 = (double2*)lds;
-  l2[idx] = make_double2(b[0], b[1]);
-  l2[PU + idx] = make_double2(b[2], b[3]);
-  l2[2 * PU + idx] = make_double2(S[0], S[1]);
-  l2[3 * PU + idx] = make_double2(S[2], S[3]);
-  l2[4 * PU + idx] = make_double2(D[0], D[1]);
-  l2[5 * PU + idx] = make_double2(D[2], D[3]);
-  l2[6 * PU + idx] = make_double2(Tn[0], Tn[1]);
-  l2[7 * PU + idx] = make_double2(Tn[2], Tn[3]);
-}
-
 // Field contribution of one pair from its LDS entry (FP32).
 __device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, float f, float ri, float dx,
                                             float dy, float dz, float bE[3], float bB[3]) {
@@ -776,7 +775,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
                                           int4 (&tab_i)[2][FastShape<T, WZ, W>::G],
                                           float4 (&tab_f)[2][FastShape<T, WZ, W>::G],
                                           double (&tab_c)[2][FastShape<T, WZ, W>::G][6],
-                                          double (&thr)[FastShape<T, WZ, W>::THR]) {
+                                          double (&thr)[FastShape<T, WZ, W>::THR], int (&qs)[2][1]) {
   using Raw = typename RawOf<T>::type;
   constexpr int G = FastShape<T, WZ, W>::G;
   constexpr int kThreads = FastShape<T, WZ, W>::KT;
@@ -826,15 +825,31 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   FpAcc fpa;
   Raw raw[NRAW];
 
-  auto make_table = [&](int rb, int buf) {
-    if (t < G) {
+  // Next round's table: the first G bricks at or after `cursor` that are
+  // not dead for this tile, among the next 64 (dead bricks -- every pair
+  // before the oldest slice -- are skipped instead of occupying round
+  // slots).  Wavefront 0 tests the 64 bricks, one per lane; slots it does
+  // not fill are marked dead, and qs[buf][0] receives the cursor after the
+  // last brick taken (after all 64 when fewer than G were live: the round
+  // is then short or empty).
+  auto make_table = [&](int cursor, int buf) {
+    if (t < 64) {
       int4 ti;
       float4 tf;
       double cc[6];
-      brick_info(p, tg, rb + t, b_end, ti, tf, cc);
-      tab_i[buf][t] = ti;
-      tab_f[buf][t] = tf;
-      for (int q = 0; q < 6; ++q) tab_c[buf][t][q] = cc[q];
+      brick_info(p, tg, cursor + t, b_end, ti, tf, cc);  // past b_end: a dead entry
+      const bool live = !(ti.z & 1);
+      const unsigned long long m = __ballot(live);
+      const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if (live && rank < G) {
+        tab_i[buf][rank] = ti;
+        tab_f[buf][rank] = tf;
+        for (int q = 0; q < 6; ++q) tab_c[buf][rank][q] = cc[q];
+      }
+      const int got = (int)__popcll(m);
+      if (t >= got && t < G) tab_i[buf][t] = make_int4(0, -1, 1, 0);
+      const unsigned long long last = __ballot(live && rank == G - 1);
+      if (t == 0) qs[buf][0] = min(got >= G ? cursor + (int)__builtin_ctzll(last) + 1 : cursor + 64, b_end);
     }
   };
   auto load_round = [&](int buf) {
@@ -853,7 +868,21 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       sl += sl < 0 ? p.capacity : 0;
       sl += sl < 0 ? p.capacity : 0;
       sl -= sl >= p.capacity ? p.capacity : 0;
-      unsigned off = (unsigned)sl * sb + ((unsigned)ti.w * kBrickCells + (unsigned)sc) * (4u * (unsigned)sizeof(T));
+      const unsigned cell_off = ((unsigned)ti.w * kBrickCells + (unsigned)sc) * (4u * (unsigned)sizeof(T));
+      unsigned off = (unsigned)sl * sb + cell_off;
+      if (p.stencil & kStencilHold) {
+        // slices before 0 read slice 0 (slot_base)
+        const int o0 = (int)((unsigned)p.slot_base * sb + cell_off);
+#pragma unroll
+        for (int r = 0; r < NRAW; ++r) {
+          const int j = j0 + r;
+          const int o = j < 0 ? o0 : (j < p.nt ? (int)off : kOutOfRange);
+          buffer_raw(rs, o, raw[r]);
+          off += sb;
+          off -= off >= p.ring_bytes_rs ? p.ring_bytes_rs : 0u;
+        }
+        return;
+      }
 #pragma unroll
       for (int r = 0; r < NRAW; ++r) {
         const int o = (unsigned)(j0 + r) < (unsigned)p.nt ? (int)off : kOutOfRange;
@@ -874,16 +903,25 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   auto write_round = [&](int buf) {
     const int4 ti = tab_i[buf][sj];
     if (ti.z & 1) return;
+    if (p.stencil & kStencilSlope) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e)
+        put_entry<true>(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1],
+                        raw[e + 2], inv_dt);
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < EPT; ++e)
-      put_entry(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1],
-                raw[e + 2], inv_dt);
+      put_entry<false>(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1],
+                       raw[e + 2], inv_dt);
   };
 
   int buf = 0;
-  if (b_begin < b_end) {
-    make_table(b_begin, 0);
+  int cursor = b_begin;
+  if (cursor < b_end) {
+    make_table(cursor, 0);
     __syncthreads();
+    cursor = qs[0][0];
     load_round(0);
   }
   // Source-cell index of a brick's first cell (fingerprints only).
@@ -897,11 +935,17 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     return s_base + (c & 1) + p.src.n[0] * (((c >> 1) & 1) + p.src.n[1] * (c >> 2));
   };
 
-  for (int rb = b_begin; rb < b_end; rb += G) {
+  // rounds continue while bricks remain: the round in `buf` was filled
+  // from bricks before `cursor`; the next one is probed from `cursor`
+  for (bool more = b_begin < b_end; more;) {
     write_round(buf);
-    make_table(rb + G, buf ^ 1);
+    const bool next = cursor < b_end;
+    if (next) make_table(cursor, buf ^ 1);
     __syncthreads();
-    if (rb + G < b_end) load_round(buf ^ 1);
+    if (next) {
+      cursor = qs[buf ^ 1][0];
+      load_round(buf ^ 1);
+    }
 
     // a wavefront whose 4x4x4 block lies wholly outside the observation
     // grid (tile padding) stages but computes nothing
@@ -1013,11 +1057,12 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         // flagged by bit 2 can have
         if (tz & 4) {
           // a brick straddling the switch-on front: skip it for this wavefront
-          // when every pair lies before slice -1 (all contributions are zero)
+          // when every pair lies before slice -1 (all contributions are zero,
+          // unless the past is held)
           int mmax = m[0];
 #pragma unroll
           for (int c = 1; c < 8; ++c) mmax = max(mmax, m[c]);
-          if (!__any(mmax >= -1 - p.a_i)) continue;
+          if (!(p.stencil & kStencilHold) && !__any(mmax >= -1 - p.a_i)) continue;
 #pragma unroll
           for (int c = 0; c < 8; ++c)
             pair_fields(lds, PU, cellbase + c * kCellStride + max(m[c], mlo), fr[c], ri[c], (c & 1) ? d1x : d0x,
@@ -1121,6 +1166,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     }
     __syncthreads();
     buf ^= 1;
+    more = next;
   }
 
   if (!valid) return;
@@ -1169,7 +1215,8 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ float4 tab_f[2][S::G];
   __shared__ double tab_c[2][S::G][6];
   __shared__ double thr[S::THR];
-  pair_body<T, WZ, FP, IDX, W>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr);
+  __shared__ int qs[2][1];
+  pair_body<T, WZ, FP, IDX, W>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr, qs);
 }
 
 // Persistent batched launch: workgroups pull (instance, workgroup id) items
@@ -1183,6 +1230,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ float4 tab_f[2][S::G];
   __shared__ double tab_c[2][S::G][6];
   __shared__ double thr[S::THR];
+  __shared__ int qs[2][1];
   __shared__ int cur;
   const int n_items = bd.counts[0];
   for (;;) {
@@ -1196,7 +1244,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
     using CP = const __attribute__((address_space(4))) PairParams;
     CP& p = *(CP*)(bd.params + inst);
-    pair_body<T, WZ, false, IDX, 32>(p, bid, lds, tab_i, tab_f, tab_c, thr);
+    pair_body<T, WZ, false, IDX, 32>(p, bid, lds, tab_i, tab_f, tab_c, thr, qs);
   }
 }
 

@@ -91,9 +91,9 @@ def test_eval_validation(case):
     elif case == "bad-dt":
         dt = 0.0
     elif case == "bad-flags":
-        opt.flags = 8
+        opt.flags = 16
     elif case == "both-flags":
-        opt.flags = J.JEFI_FLAG_INDEX_GUARD | J.JEFI_FLAG_INDEX_TABLE
+        opt.flags = J.JEFI_FLAG_INDEX_GUARD | J.JEFI_FLAG_INDEX_TABLE | J.JEFI_FLAG_PAST_HOLD
     elif case == "bad-tile":
         opt.tile_config = 3
     st = J.lib.jefi_eval_fields(src_p, C.byref(h), dt, nt, C.byref(obs), t, C.byref(fields),
