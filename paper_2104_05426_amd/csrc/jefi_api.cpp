@@ -391,8 +391,11 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
     if (max_splits < 1) max_splits = 1;
     if (splits > max_splits) splits = max_splits;
     if (splits < 1) splits = 1;
+    // a multiple of 8 splits lets the launch deal them round-robin over the
+    // 8 XCDs (balanced shares of the source); the last ones may be empty
+    if (splits >= 8) splits &= ~7LL;
     long long bps = (p.n_bricks + splits - 1) / splits;
-    splits = (p.n_bricks + bps - 1) / bps;
+    if (splits < 8) splits = (p.n_bricks + bps - 1) / bps;
     p.n_splits = (int)splits;
     p.bricks_per_split = (int)bps;
     p.n_wg = (int)((long long)p.n_tiles * splits);

@@ -72,11 +72,21 @@ __device__ __forceinline__ double r2_threshold(int N, double af, double icdt) {
   return __longlong_as_double((long long)lo);
 }
 
-// Map the hardware workgroup id so that consecutive logical ids land on the
-// same XCD (workgroups are dealt round-robin over the 8 XCDs).
-__device__ __forceinline__ int xcd_remap(int bid, int n) {
-  int q = n >> 3, r = n & 7;
-  int x = bid & 7, l = bid >> 3;
+// Logical workgroup (split * n_tiles + tile) of hardware workgroup `bid`.
+// The hardware deals workgroups round-robin over the 8 XCDs (each with its
+// own L2).  With a multiple of 8 splits, XCD x takes splits x, x+8, x+16,
+// ..., each with all its tiles in a row: the workgroups one XCD runs at a
+// time read the source bricks of one split, and every XCD gets splits from
+// all over the source, so their shares of live pairs match (contiguous
+// splits would hand one XCD the edge of the source and another its
+// middle).  Otherwise consecutive logical ids stay on one XCD.
+__device__ __forceinline__ int xcd_remap(int bid, int n, int n_tiles, int n_splits) {
+  const int x = bid & 7, l = bid >> 3;
+  if ((n_splits & 7) == 0) {
+    const int k = l / n_tiles;
+    return (x + 8 * k) * n_tiles + (l - k * n_tiles);
+  }
+  const int q = n >> 3, r = n & 7;
   return x * q + min(x, r) + l;
 }
 
@@ -366,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
   __shared__ float4 tab_f[G];
   __shared__ double tab_c[G][6];
 
-  const int bid = xcd_remap((int)blockIdx.x, p.n_wg);
+  const int bid = xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits);
   const int split = bid / p.n_tiles;
   const int tile = bid - split * p.n_tiles;
   const TileGeom tg = tile_geom(p, tile);
@@ -1216,7 +1226,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ double tab_c[2][S::G][6];
   __shared__ double thr[S::THR];
   __shared__ int qs[2][1];
-  pair_body<T, WZ, FP, IDX, W>(p, xcd_remap((int)blockIdx.x, p.n_wg), lds, tab_i, tab_f, tab_c, thr, qs);
+  pair_body<T, WZ, FP, IDX, W>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab_i, tab_f, tab_c, thr, qs);
 }
 
 // Persistent batched launch: workgroups pull (instance, workgroup id) items
