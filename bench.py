@@ -55,6 +55,9 @@ def profiled_traffic(workload):
         return None
 
 
+FP32_RANGE_FLOOR = 1e-30  # fields smaller than this come from FP32 inputs near or below underflow
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -358,8 +361,14 @@ def run_serve_workload(args):
             log(f"  fp64 baseline {i}")
     wall64 = time.perf_counter() - t0
     log(f"fp64 one-launch-per-request: {len(reqs)/wall64:.1f} req/s")
-    worst = 0.0
+    # Sessions whose blobs have drifted far from their box have fields below
+    # FP32 range (their FP32 history rounds to zero): relative errors there
+    # say nothing about arithmetic, so they are counted and left out.
+    worst, below = 0.0, 0
     for i in sorted(keep_fp64):
+        if max(np.abs(res64[i][0]).max(initial=0.0), np.abs(res64[i][1]).max(initial=0.0)) < FP32_RANGE_FLOOR:
+            below += 1
+            continue
         worst = max(worst, max_rel_l2(outs_p[i][0].astype(np.float64), outs_p[i][1].astype(np.float64),
                                       res64[i][0], res64[i][1]))
     # a few requests against the oracle
@@ -374,6 +383,9 @@ def run_serve_workload(args):
         win = workloads.blob_history(g, sp["blobs"], list(range(st - cap + 1, st + 1)), sp["dt"])
         sel = np.sort(rng.choice(obs_of[i].size, size=min(16, obs_of[i].size), replace=False))
         Er, Br = oracle.eval_fields(g, obs_of[i], win, sp["dt"], st * sp["dt"], 0.0, st, 1.0, None, sel=sel)
+        if max(np.abs(Er).max(initial=0.0), np.abs(Br).max(initial=0.0)) < FP32_RANGE_FLOOR:
+            below += 1
+            continue
         worst_or = max(worst_or, max_rel_l2(outs_p[i][0][:, sel].astype(np.float64),
                                             outs_p[i][1][:, sel].astype(np.float64), Er, Br))
     total_pairs = float(pairs.sum())
@@ -397,7 +409,8 @@ def run_serve_workload(args):
         "fp64_one_launch_per_request": {"req_per_s": round(len(reqs) / wall64, 2),
                                         "value": round(total_pairs / wall64 / 1e9, 3)},
         "server_over_fp64_baseline": round(wall64 / wall_o, 3),
-        "parity": {"max_rel_l2_vs_fp64_sampled": float(f"{worst:.3e}"),
+        "parity": {"max_rel_l2_vs_fp64_sampled": float(f"{worst:.3e}"), "sampled": len(keep),
+                   "sampled_below_fp32_range": below,
                    "max_rel_l2_vs_oracle_sampled": float(f"{worst_or:.3e}"), "tol": 1e-5,
                    "ok": bool(worst <= 1e-5 and worst_or <= 1e-5)},
     }

@@ -432,6 +432,23 @@ def test_ring_above_2gib_matches_small_ring(prec):
     _assert_fields(outs[0][0][:, sel], outs[0][1][:, sel], Er, Br, TOL[prec], f"ring > 2 GiB {prec}")
 
 
+def test_history_below_fp32_range():
+    """Sources of order 1e-60 (a blob far outside a small box): the FP64
+    path matches the oracle; the FP32 path receives an all-zero history
+    after rounding and returns exactly the fields of those inputs, zero."""
+    G = _gpu()
+    p0 = workloads.config_tiny()
+    hist = 1e-60 * np.random.default_rng(4).normal(size=p0.hist.shape)
+    p = Problem("tiny-1e-60", p0.src, p0.obs, hist, p0.dt, p0.t, p0.t0, p0.newest, p0.c, p0.screen)
+    Er, Br = oracle.eval_problem(p)
+    assert 0.0 < np.abs(Er).max() < 1e-50
+    Eg, Bg = G.gpu_eval(p, "f64")
+    _assert_fields(Eg, Bg, Er, Br, TOL["f64"], "1e-60 sources f64")
+    assert not np.any(hist.astype(np.float32))
+    Eg, Bg = G.gpu_eval(p, "f32")
+    assert np.all(Eg == 0.0) and np.all(Bg == 0.0)
+
+
 def test_deterministic_repeat():
     G = _gpu()
     p = _medium()
