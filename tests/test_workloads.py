@@ -91,3 +91,18 @@ def test_draws_are_reproducible_and_in_range():
         assert all(-0.8 <= c <= 0.8 for c in bl.centre)
         assert 0.05 <= bl.sigma <= 0.2 and -1.0 <= bl.q <= 1.0
         assert math.sqrt(sum(x * x for x in bl.velocity)) <= 0.8 + 1e-12
+
+
+def test_paper_source_factors_compose_the_paper_histories():
+    """Time factor x spatial pattern (the form the accuracy study builds on
+    the device) gives exactly the paper's constant and sinusoidal histories."""
+    import workloads as W
+    g = W.centred_grid((5, 4, 3), 0.4)
+    ph = W.cell_centres(g).sum(1)
+    steps = [-2, 0, 3, 7]
+    for kind, fn, pr, pj in [("constant", W.constant_step_history, np.ones_like(ph), np.ones_like(ph)),
+                             ("sinusoidal", W.sinusoidal_history, np.cos(ph), np.sin(ph))]:
+        h = fn(g, steps, 0.3)
+        for si, s in enumerate(steps):
+            a, b = W.paper_source_factors(kind, s * 0.3)
+            assert np.array_equal(h[si], np.stack([a * pr, b * pj, b * pj, b * pj])), (kind, s)

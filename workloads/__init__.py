@@ -151,6 +151,20 @@ def sinusoidal_history(g: Grid, steps: Sequence[int] | int, dt: float,
     return out
 
 
+def paper_source_factors(kind: str, t: float) -> Tuple[float, float]:
+    """The paper's analytic sources as (time factor of rho, time factor of
+    each J component) times fixed spatial patterns: "constant" -> patterns
+    1 and 1; "sinusoidal" -> patterns cos(x + y + z) and sin(x + y + z).
+    Zero before t = 0 (sections "Constant sources", "Sinusoidal sources")."""
+    if t < 0.0:
+        return 0.0, 0.0
+    if kind == "constant":
+        return 1.0, 1.0
+    if kind == "sinusoidal":
+        return 3.0 * (math.cos(t) - 1.0), math.sin(t)
+    raise ValueError(kind)
+
+
 def draw_blobs(rng: np.random.Generator, k: int, box: Tuple[float, float]) -> List[Blob]:
     """Blob parameters in a fixed draw order: centres (3k, uniform in the
     box), sigma (k, uniform in [0.05, 0.2]), charge (k, uniform in [-1, 1]),
