@@ -559,6 +559,151 @@ def run_accuracy_workload(args):
             "cases": res}
 
 
+# The paper's per-step timing table (section "Parameter dependence",
+# Table 4): coincident n^3 source and observation grids ("ntg" [n^3, n^3])
+# with a history of lts + 1 slices; per step, one new slice goes host to
+# device, the fields are evaluated, E and B come back to the host.  The
+# paper's V100 figures (exec, [DToH, HToD] in s at lts 500) for context.
+PAPER_TABLE4 = {20: (1.001, 0.0004, 0.002), 60: (2.720, 0.002, 0.004), 70: (4.858, 0.009, 0.005),
+                100: (32.565, 0.027, 0.009), 160: (521.970, 0.060, 0.042)}
+
+
+def run_paper_steps(args):
+    """Per-step time at the paper's grid sizes in three couplings:
+    serial (copy in, push, evaluate, copy out, as the paper times it);
+    overlapped (step s's E/B copy out and slice s+1's copy in run on a copy
+    stream while step s+1 evaluates); device producer (the slice is made on
+    the device and pushed from there, E/B copy out overlapped)."""
+    import torch
+    import workloads
+    import paper_2104_05426_amd as J
+    lts, dt = 500, 0.05
+    sizes = [20, 60, 70, 100, 160] if not args.paper_sizes else [int(v) for v in args.paper_sizes.split(",")]
+    comp = torch.cuda.current_stream()
+    copy = torch.cuda.Stream()
+    out = {}
+    for n in sizes:
+        dx = 6.0 / n
+        g = workloads.Grid((n, n, n), (-3.0 + 0.5 * dx,) * 3, (dx,) * 3)
+        ns = g.size
+        ax = torch.arange(n, dtype=torch.float64, device="cuda") * dx + (-3.0 + 0.5 * dx)
+        zz, yy, xx = torch.meshgrid(ax, ax, ax, indexing="ij")
+        phase = (xx + yy + zz).reshape(-1)
+        p_rho, p_j = torch.cos(phase).float(), torch.sin(phase).float()
+        del zz, yy, xx, phase
+
+        def make_slice(k, dst):
+            a, b = workloads.paper_source_factors("sinusoidal", k * dt)
+            torch.mul(p_rho, a, out=dst[0])
+            torch.mul(p_j, b, out=dst[1])
+            dst[2].copy_(dst[1])
+            dst[3].copy_(dst[1])
+
+        store = torch.empty(J.jefi_history_bytes(g, lts + 1, J.JEFI_F32), dtype=torch.uint8, device="cuda")
+        h = J.jefi_history_init(store, g, lts + 1, J.JEFI_F32)
+        dev_slice = [torch.empty((4, ns), dtype=torch.float32, device="cuda") for _ in range(2)]
+        for k in range(lts + 1):
+            make_slice(k, dev_slice[0])
+            J.jefi_history_push(h, g, dev_slice[0])
+        host_slice = [torch.empty((4, ns), dtype=torch.float32, pin_memory=True) for _ in range(2)]
+        E = [torch.empty((3, ns), dtype=torch.float32, device="cuda") for _ in range(2)]
+        B = [torch.empty((3, ns), dtype=torch.float32, device="cuda") for _ in range(2)]
+        hE = [torch.empty((3, ns), dtype=torch.float32, pin_memory=True) for _ in range(2)]
+        hB = [torch.empty((3, ns), dtype=torch.float32, pin_memory=True) for _ in range(2)]
+        opt = J.jefi_options_default(precision=J.JEFI_PREC_F32_COMP)
+        steps = 2 if n >= 160 else 3
+        warm = 0 if n >= 160 else 1
+        k_next = [lts + 1]
+
+        def host_make(i):
+            make_slice(k_next[0] + i, dev_slice[1])
+            host_slice[i % 2].copy_(dev_slice[1])
+        # serial: copy in, push, evaluate, copy out, each timed
+        parts = []
+        for i in range(warm + steps):
+            host_make(0)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            dev_slice[0].copy_(host_slice[0], non_blocking=True)
+            ev[1].record()
+            J.jefi_history_push(h, g, dev_slice[0])
+            J.jefi_eval_fields(g, h, dt, lts + 1, g, h.newest * dt, E[0], B[0], opt)
+            ev[2].record()
+            hE[0].copy_(E[0], non_blocking=True)
+            hB[0].copy_(B[0], non_blocking=True)
+            ev[3].record()
+            torch.cuda.synchronize()
+            k_next[0] += 1
+            if i >= warm:
+                parts.append([ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])])
+        parts = np.array(parts) / 1e3
+        serial = float(parts.sum(axis=1).mean())
+
+        def pipelined(device_producer):
+            host_make(0)
+            host_make(1)
+            torch.cuda.synchronize()
+            done = [torch.cuda.Event() for _ in range(steps)]
+            arrived = [torch.cuda.Event() for _ in range(steps)]
+            copied = [torch.cuda.Event() for _ in range(steps)]
+            t0 = time.perf_counter()
+            if not device_producer:
+                with torch.cuda.stream(copy):
+                    dev_slice[0].copy_(host_slice[0], non_blocking=True)
+                    arrived[0].record(copy)
+            for i in range(steps):
+                if i >= 2:
+                    comp.wait_event(copied[i - 2])  # E/B[i % 2] of step i - 2 are on the host
+                if device_producer:
+                    make_slice(k_next[0] + i, dev_slice[i % 2])
+                else:
+                    comp.wait_event(arrived[i])
+                J.jefi_history_push(h, g, dev_slice[i % 2])
+                J.jefi_eval_fields(g, h, dt, lts + 1, g, h.newest * dt, E[i % 2], B[i % 2], opt)
+                done[i].record(comp)
+                with torch.cuda.stream(copy):
+                    if not device_producer and i + 1 < steps:
+                        copy.wait_event(done[i - 1] if i > 0 else arrived[0])
+                        dev_slice[(i + 1) % 2].copy_(host_slice[(i + 1) % 2], non_blocking=True)
+                        arrived[i + 1].record(copy)
+                    copy.wait_event(done[i])
+                    hE[i % 2].copy_(E[i % 2], non_blocking=True)
+                    hB[i % 2].copy_(B[i % 2], non_blocking=True)
+                    copied[i].record(copy)
+            torch.cuda.synchronize()
+            k_next[0] += steps
+            return (time.perf_counter() - t0) / steps
+
+        log(f"paper-steps n={n}: serial {serial:.4f} s/step")
+        over = pipelined(False)
+        log(f"paper-steps n={n}: overlapped {over:.4f} s/step")
+        dev = pipelined(True)
+        pairs = float(ns) * ns
+        ref = PAPER_TABLE4.get(n)
+        row = {"pairs": pairs, "exec_s": round(float(parts[:, 1].mean()), 5),
+               "dtoh_s": round(float(parts[:, 2].mean()), 5), "htod_s": round(float(parts[:, 0].mean()), 5),
+               "serial_step_s": round(serial, 5), "overlapped_step_s": round(over, 5),
+               "device_producer_step_s": round(dev, 5),
+               "exec_G_pairs_per_s": round(pairs / float(parts[:, 1].mean()) / 1e9, 2)}
+        if ref:
+            row["paper_v100_lts500"] = {"exec_s": ref[0], "dtoh_s": ref[1], "htod_s": ref[2]}
+            row["exec_speedup_vs_paper"] = round(ref[0] / float(parts[:, 1].mean()), 1)
+        log(f"paper-steps n={n}: {json.dumps(row)}")
+        out[f"{n}^3"] = row
+        del store, dev_slice, host_slice, E, B, hE, hB, p_rho, p_j
+        torch.cuda.empty_cache()
+    big = out[f"{sizes[-1]}^3"]
+    return {"metric": "G source-obs pairs/s per evaluation at the paper's per-step configurations "
+                      "(ntg [n^3, n^3], lts 500)", "value": big["exec_G_pairs_per_s"], "unit": "G pairs/s",
+            "n_gpus": 1, "steps": 2, "warmup": 0, "ms_per_step": round(big["serial_step_s"] * 1e3, 2),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (the paper's sinusoidal source)",
+            "config": {"workload": f"paper-steps: coincident n^3 grids over [-3,3]^3, n = {sizes}, lts 500, "
+                                   "dt 0.05, FP32-compensated; serial / overlapped / device-producer steps"},
+            "sizes": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -571,6 +716,8 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-companion", action="store_true",
                     help="skip the 32^3 single-instance line reported beside the 64^3 headline")
+    ap.add_argument("--paper-sizes", default="",
+                    help="comma-separated grid edges for --workload paper-steps (default 20,60,70,100,160)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the time-stencil variants of the headline workload")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
@@ -605,6 +752,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(run_serve_workload(args)), flush=True)
+        return
+    if args.workload == "paper-steps":
+        print(json.dumps(run_paper_steps(args)), flush=True)
         return
     if args.workload == "accuracy":
         print(json.dumps(run_accuracy_workload(args)), flush=True)
