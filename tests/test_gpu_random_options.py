@@ -1,0 +1,45 @@
+"""Randomised parity sweep over option combinations: ragged random problems
+(partial tiles and bricks, unequal spacings, c != 1, screening widths from
+0 to a few cells, windows not starting at step 0), each evaluated with a
+random index mode, time-stencil reading and launch shape in both
+precisions, at a time inside the window or before it; fields against the
+oracle with the same reading, fingerprints against the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.compare import rel_l2
+from tests.test_gpu_parity import _ragged_problem
+from workloads import Problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_option_combinations(seed):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from tests import _gpu as G
+    rng = np.random.default_rng(1000 + seed)
+    p = _ragged_problem(200 + seed, smooth=bool(seed % 3))
+    if seed % 4 == 3:  # evaluation time before the window's oldest slice
+        t_old = p.t0 + (p.newest - p.nt + 1) * p.dt
+        p = Problem(p.name + "-early", p.src, p.obs, p.hist, p.dt, t_old - float(rng.uniform(0.2, 4.0)) * p.dt,
+                    p.t0, p.newest, p.c, p.screen)
+    idx = seed % 3                               # auto, guard, table
+    stencil = (seed // 3) % 4                    # oracle bits: 1 slope, 2 hold (each pair twice)
+    flags = idx | (stencil << 2)                 # JEFI_FLAG_DERIV_SLOPE = 4, JEFI_FLAG_PAST_HOLD = 8
+    tile = int(rng.integers(0, 3))
+    Er, Br = oracle.eval_problem(p, stencil=stencil)
+    fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+    for prec in ("f64", "f32"):
+        Eg, Bg = G.gpu_eval(p, prec, tile=tile, flags=flags)
+        e, _ = rel_l2(Eg, Er)
+        b, _ = rel_l2(Bg, Br)
+        print(f"{p.name} {prec} flags {flags} tile {tile}: {max(e + b):.2e}", flush=True)
+        assert np.all(np.isfinite(Eg)) and np.all(np.isfinite(Bg))
+        assert max(e + b) <= TOL[prec], (p.name, prec, flags, tile, e, b)
+        assert np.array_equal(G.gpu_fingerprint(p, prec, tile=tile, flags=flags), fp_ref), (p.name, prec, flags)
