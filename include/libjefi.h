@@ -241,6 +241,8 @@ typedef struct {
   int32_t max_inflight;     /* batches on the device at once, 1..8 (0 = 2) */
   int32_t max_batch;        /* requests per batch (0 = 256) */
   int32_t max_queue;        /* waiting requests before submit returns EBUSY (0 = 65536) */
+  uint32_t flags;           /* jefi_options.flags of every evaluation (index mode, time-stencil
+                               readings); 0 = defaults; invalid combinations: EINVAL at create */
 } jefi_server_config;
 
 typedef struct {

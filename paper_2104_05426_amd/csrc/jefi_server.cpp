@@ -390,6 +390,7 @@ void admit_and_launch(jefi_server* sv) {
     jefi_options opt;
     jefi_options_default(&opt);
     opt.precision = sv->cfg.precision;
+    opt.flags = sv->cfg.flags;
     rc = jefi_eval_batch(probs.data(), (int32_t)probs.size(), &opt, st);
     if (rc == JEFI_EDEVICE) set_sticky(sv, hipErrorUnknown, jefi_last_error());
   }
@@ -467,6 +468,9 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
   if (!cfg || !out) return JEFI_EINVAL;
   if (!cfg->arena || cfg->arena_bytes < Arena::kGranule) return JEFI_EINVAL;
   if (cfg->precision != JEFI_PREC_F64 && cfg->precision != JEFI_PREC_F32_COMP) return JEFI_EINVAL;
+  const uint32_t known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_PAST_HOLD;
+  const uint32_t both = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE;
+  if ((cfg->flags & ~known) != 0 || (cfg->flags & both) == both) return JEFI_EINVAL;
   jefi_server* sv = new jefi_server();
   sv->cfg = *cfg;
   if (sv->cfg.max_inflight < 1) sv->cfg.max_inflight = 2;

@@ -6,6 +6,7 @@
 // Test infrastructure only: nothing here computes fields.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
@@ -185,7 +186,10 @@ jefi_status jefi_history_push(jefi_history* h, const jefi_grid* src, const void*
 
 // E[0][o] = sum over the window (oldest first, j = 0..nt-1) of (j + 1) * rho
 // of cell 0 in that slot; E[1][o] = newest step; E[2][o] = t; B[c][o] = o.
+std::atomic<unsigned> g_last_batch_flags{0};
+
 jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream) {
+  g_last_batch_flags.store(opt->flags);
   // the whole batch "runs" for a while before it reads any ring, which
   // leaves room for a later batch to overtake it if nothing orders them
   const int sleep_us = g_eval_sleep_us;

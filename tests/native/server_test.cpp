@@ -15,6 +15,7 @@
 #include "../../include/libjefi.h"
 
 extern int g_eval_sleep_us;
+extern std::atomic<unsigned> g_last_batch_flags;
 
 static std::atomic<int> g_fail{0};
 #define CHECK(c)                                                \
@@ -63,7 +64,8 @@ struct Pending {
   std::vector<float> slice;
 };
 
-jefi_server* make_server(size_t arena_bytes, int max_inflight, int max_queue, std::vector<char>& arena) {
+jefi_server* make_server(size_t arena_bytes, int max_inflight, int max_queue, std::vector<char>& arena,
+                         uint32_t flags = 0) {
   arena.assign(arena_bytes, 0);
   jefi_server_config cfg;
   std::memset(&cfg, 0, sizeof cfg);
@@ -73,6 +75,7 @@ jefi_server* make_server(size_t arena_bytes, int max_inflight, int max_queue, st
   cfg.max_inflight = max_inflight;
   cfg.max_batch = 64;
   cfg.max_queue = max_queue;
+  cfg.flags = flags;
   jefi_server* sv = nullptr;
   CHECK(jefi_server_create(&cfg, &sv) == JEFI_OK);
   return sv;
@@ -257,6 +260,32 @@ void time_after_newest_fails_at_admission() {
   CHECK(jefi_server_destroy(sv) == JEFI_OK);
 }
 
+void option_flags() {
+  // invalid combinations are refused at create; valid ones reach every evaluation
+  std::vector<char> arena(1 << 20);
+  jefi_server_config cfg;
+  std::memset(&cfg, 0, sizeof cfg);
+  cfg.arena = arena.data();
+  cfg.arena_bytes = arena.size();
+  cfg.precision = JEFI_PREC_F32_COMP;
+  jefi_server* bad = nullptr;
+  cfg.flags = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE;
+  CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
+  cfg.flags = 64;
+  CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
+  std::vector<char> ar;
+  const uint32_t flags = JEFI_FLAG_PAST_HOLD | JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_INDEX_TABLE;
+  jefi_server* sv = make_server(8 << 20, 2, 64, ar, flags);
+  g_eval_sleep_us = 0;
+  std::vector<Session> ss = {{41, 3, 0}};
+  open_sessions(sv, ss, 2);
+  Pending p;
+  submit(sv, ss[0], p, 2);
+  check_result(sv, p);
+  CHECK(g_last_batch_flags.load() == flags);
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
 }  // namespace
 
 int main() {
@@ -265,6 +294,7 @@ int main() {
   eviction();
   full_queue_and_rejections();
   time_after_newest_fails_at_admission();
+  option_flags();
   if (g_fail.load() == 0) std::printf("server ok\n");
   return g_fail.load() == 0 ? 0 : 1;
 }

@@ -48,7 +48,7 @@ def _obs_for(sess, rng):
     return Grid((eo, eo, eo), tuple(sess["src"].origin[a] + m * dx for a in range(3)), (dx, dx, dx))
 
 
-def _solo(J, src, hist_window, dt, newest, obs, t, prec="f32"):
+def _solo(J, src, hist_window, dt, newest, obs, t, prec="f32", flags=0):
     """One evaluation alone: a ring holding exactly the window."""
     import torch
     f64 = prec == "f64"
@@ -56,13 +56,14 @@ def _solo(J, src, hist_window, dt, newest, obs, t, prec="f32"):
     E = torch.empty((3, max(obs.size, 1)), dtype=torch.float64 if f64 else torch.float32, device="cuda")
     B = torch.empty_like(E)
     opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if f64 else J.JEFI_PREC_F32_COMP)
+    opt.flags = flags
     J.jefi_eval_fields(src, h, dt, hist_window.shape[0], obs, t, E[:, :obs.size], B[:, :obs.size], opt)
     torch.cuda.synchronize()
     return E[:, :obs.size].double().cpu().numpy(), B[:, :obs.size].double().cpu().numpy()
 
 
 def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32", max_inflight=2,
-                blocker=False):
+                blocker=False, flags=0):
     """n_req requests over n_sessions sessions, submitted back to back.
     blocker: first submit one large request of an extra session, so that
     (with max_inflight = 1) the others queue up behind it and are batched."""
@@ -73,7 +74,7 @@ def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32
     f64 = prec == "f64"
     ndt = np.float64 if f64 else np.float32
     sv = J.Server(arena, precision=J.JEFI_PREC_F64 if f64 else J.JEFI_PREC_F32_COMP, max_inflight=max_inflight,
-                  max_batch=64)
+                  max_batch=64, flags=flags)
     if blocker:
         bsrc = centred_grid((48, 48, 48), 1.6 / 48)
         bh = blob_history(bsrc, workloads.draw_blobs(np.random.default_rng(1), 3, (-0.8, 0.8)), 8, 0.8 / 48)
@@ -114,7 +115,7 @@ def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32
     return reqs, results, stats, full
 
 
-def _check_solo(J, reqs, full, n_oracle=4, prec="f32"):
+def _check_solo(J, reqs, full, n_oracle=4, prec="f32", flags=0):
     rng = np.random.default_rng(1)
     for i, r in enumerate(reqs):
         s = r["s"]
@@ -123,14 +124,14 @@ def _check_solo(J, reqs, full, n_oracle=4, prec="f32"):
         if prec == "f32":
             window = window.astype(np.float32).astype(np.float64)
         t = r["newest"] * s["dt"]
-        Es, Bs = _solo(J, s["src"], window, s["dt"], r["newest"], r["obs"], t, prec)
+        Es, Bs = _solo(J, s["src"], window, s["dt"], r["newest"], r["obs"], t, prec, flags)
         e, _ = rel_l2(r["E"].astype(np.float64), Es)
         b, _ = rel_l2(r["B"].astype(np.float64), Bs)
         assert max(e + b) <= SOLO_TOL[prec], (i, e, b)
         if i < n_oracle:
             p = Problem("srv", s["src"], r["obs"], window, s["dt"], t, 0.0, r["newest"], 1.0,
                         workloads.default_screen(s["src"]))
-            Er, Br = oracle.eval_problem(p)
+            Er, Br = oracle.eval_problem(p, stencil=(flags >> 2) & 3)
             e, _ = rel_l2(r["E"].astype(np.float64), Er)
             b, _ = rel_l2(r["B"].astype(np.float64), Br)
             assert max(e + b) <= ORACLE_TOL[prec], (i, e, b)
@@ -167,6 +168,19 @@ def test_server_fp64_results_equal_solo():
     reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=4, n_req=24, seed=8, prec="f64")
     assert stats["completed"] == 24 and stats["failed"] == 0
     _check_solo(J, reqs, full, n_oracle=3, prec="f64")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_server_with_stencil_flags(prec):
+    """A server whose evaluations use both alternative stencil readings
+    (slope derivative, held past) and the table index mode: every result
+    equals the same evaluation alone with those flags, and the oracle with
+    those readings."""
+    J = _gpu()
+    flags = J.JEFI_FLAG_DERIV_SLOPE | J.JEFI_FLAG_PAST_HOLD | (J.JEFI_FLAG_INDEX_TABLE if prec == "f32" else 0)
+    reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=4, n_req=20, seed=12, prec=prec, flags=flags)
+    assert stats["completed"] == 20 and stats["failed"] == 0
+    _check_solo(J, reqs, full, n_oracle=3, prec=prec, flags=flags)
 
 
 def test_server_evicts_and_rematerialises():
