@@ -49,6 +49,8 @@ PIN_CALLS = [
     lambda: pins.test_held_past_constant_history_is_static_at_any_time(2),
     lambda: pins.test_held_past_linear_history(2),
     lambda: pins.test_held_past_linear_history(3),
+    pins.test_voxelised_uniform_sphere_is_coulomb_outside,
+    pins.test_uniform_charge_and_current_box_match_the_continuum,
 ]
 
 

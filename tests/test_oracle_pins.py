@@ -385,6 +385,69 @@ def test_saturation_for_constant_sources():
     assert np.allclose(B1, B_ref * dom / FOUR_PI, rtol=1e-12)
 
 
+def _static_fields(src, rho, J, pts, dt=0.5):
+    """Oracle fields of time-independent sources (every stencil inside the
+    stored history, so all backward differences vanish) at the points."""
+    R = max(np.linalg.norm(np.asarray(p) - np.asarray(c)) for p in pts for c in _centres(src)[[0, -1]])
+    nt = int(math.ceil((R + 2.0) / dt)) + 3
+    hist = np.zeros((nt, 4, src.size))
+    hist[:, 0, :] = rho
+    hist[:, 1:4, :] = np.asarray(J, dtype=np.float64).reshape(3, -1) if np.ndim(J) > 1 else \
+        np.asarray(J, dtype=np.float64)[:, None] * np.ones(src.size)[None, :]
+    Es, Bs = [], []
+    for p in pts:
+        g = Grid((1, 1, 1), tuple(float(v) for v in p), (1.0, 1.0, 1.0))
+        E, B = oracle.eval_fields(src, g, hist, dt, t=(nt - 1) * dt, screen=(0, 0, 0))
+        Es.append(E[:, 0])
+        Bs.append(B[:, 0])
+    return np.array(Es).T, np.array(Bs).T
+
+
+def test_voxelised_uniform_sphere_is_coulomb_outside():
+    """Cells of a cubic grid whose centres lie within radius 0.5 carry unit
+    charge density.  Outside, the field is that of the point charge
+    Q = (cells) * h^3: the voxel set has cubic symmetry, so its dipole and
+    quadrupole moments vanish and the relative deviation falls off like
+    (a/r)^4 (the l = 4 moment)."""
+    h, a = 0.1, 0.5
+    src = centred_grid((11, 11, 11), h)
+    c = _centres(src)
+    rho = (np.linalg.norm(c, axis=1) <= a + 1e-12).astype(np.float64)
+    Q = rho.sum() * h ** 3
+    u = np.array([0.48, -0.36, 0.8])
+    u /= np.linalg.norm(u)
+    dists = [1.5, 3.0, 6.0]
+    E, _ = _static_fields(src, rho, (0.0, 0.0, 0.0), [d * u for d in dists])
+    devs = []
+    for i, d in enumerate(dists):
+        ref = Q / (FOUR_PI * d * d) * u
+        devs.append(np.linalg.norm(E[:, i] - ref) / np.linalg.norm(ref))
+    assert devs[0] < 0.02 and devs[2] < 1e-4, devs
+    for k in (1, 2):
+        assert 1 / 32 < devs[k] / devs[k - 1] < 1 / 8, devs   # ~ (1/2)^4
+
+
+def test_uniform_charge_and_current_box_match_the_continuum():
+    """A box of uniform charge density 1 and uniform current J: outside it,
+    E is the closed-form field of a uniformly charged box and B = J x E (the
+    static limits: Coulomb and Biot-Savart).  The cell sums are midpoint
+    rules whose h^2 term is proportional to the Laplacian of the kernel,
+    zero outside the sources (harmonic), so the error falls like h^4."""
+    from tests.continuum import box_fields
+    J = np.array([0.3, -0.7, 0.4])
+    pts = [np.array([1.3, 0.2, -0.4]), np.array([-0.9, 1.1, 0.7]), np.array([0.1, -0.2, 1.6])]
+    E_ex = box_fields(np.array(pts), (-0.5,) * 3, (0.5,) * 3)
+    B_ex = np.cross(J[None, :], E_ex.T).T
+    errs = []
+    for n in (4, 8, 16):
+        src = centred_grid((n, n, n), 1.0 / n)
+        E, B = _static_fields(src, 1.0, J, pts)
+        errs.append(max(np.abs(E - E_ex).max() / np.abs(E_ex).max(), np.abs(B - B_ex).max() / np.abs(B_ex).max()))
+    assert errs[0] < 1e-4 and errs[2] < 1e-6, errs
+    for k in (1, 2):
+        assert 1 / 32 < errs[k] / errs[k - 1] < 1 / 8, errs   # ~ (1/2)^4
+
+
 def _random_problem(rng, n_src=(3, 2, 3), n_obs=(2, 3, 2)):
     sp = tuple(rng.uniform(0.05, 0.15, 3))
     src = Grid(n_src, tuple(rng.uniform(-0.2, 0.0, 3)), sp)
