@@ -845,7 +845,15 @@ def main():
         Er64, Br64 = oracle.eval_fields(p.src, p.obs, win64, p.dt, p.t0 + last64 * p.dt, p.t0, last64, p.c,
                                         p.screen, sel=sel)
         err64 = max_rel_l2(r64["E"][:, sel], r64["B"][:, sel], Er64, Br64)
+        from oracle.compare import rel_l2
+
+        def per_component(Eg, Bg, Er_, Br_):
+            e, _ = rel_l2(Eg, Er_)
+            b, _ = rel_l2(Bg, Br_)
+            return {k: float(f"{v:.3e}") for k, v in zip(("Ex", "Ey", "Ez", "Bx", "By", "Bz"), e + b)}
         res["parity"] = {"sampled_points": int(len(sel)), "max_rel_l2_f32": float(f"{err32:.3e}"),
+                         "rel_l2_f32_per_component": per_component(r32["E"][:, sel], r32["B"][:, sel], Er, Br),
+                         "rel_l2_f64_per_component": per_component(r64["E"][:, sel], r64["B"][:, sel], Er64, Br64),
                          "max_rel_l2_f32_vs_fp32_inputs": float(f"{err32_arith:.3e}"),
                          "max_rel_l2_f64": float(f"{err64:.3e}"), "tol": 1e-5, "tol_f64": 1e-12,
                          "ok": bool(err32 <= 1e-5 and err64 <= 1e-12)}
