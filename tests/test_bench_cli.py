@@ -1,6 +1,5 @@
 """bench.py's command-line contract on the CPU: more than one GPU is refused
-with a message (this build is one-GPU), and the argument parser knows every
-workload mode the documentation names."""
+with a message (this build is one-GPU), and --help lists the options."""
 import os
 import subprocess
 import sys
