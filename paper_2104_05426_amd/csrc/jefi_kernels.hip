@@ -22,9 +22,10 @@
 //     identical to the FP64 decision;
 //   * screening is tested per pair (canonical FP64) only in bricks whose box
 //     comes within the screening width of the tile box;
-//   * FP32 per-round partial sums feed compensated (two-sum) FP32 running
-//     totals; the per-point totals are reduced in FP64 across splits by the
-//     epilogue in a fixed order.
+//   * FP32 block sums over two staging rounds (the fast pair kernels) or one
+//     (the chunked kernel) feed compensated (two-sum) FP32 running totals;
+//     the per-point totals are reduced in FP64 across splits by the epilogue
+//     in a fixed order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -947,6 +948,10 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
 
   // rounds continue while bricks remain: the round in `buf` was filled
   // from bricks before `cursor`; the next one is probed from `cursor`
+  // FP32 block sums of two rounds (up to 64 pairs per lane), then an
+  // error-free two-sum into the running totals
+  float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
+  int n_blk = 0;
   for (bool more = b_begin < b_end; more;) {
     write_round(buf);
     const bool next = cursor < b_end;
@@ -960,7 +965,6 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     // a wavefront whose 4x4x4 block lies wholly outside the observation
     // grid (tile padding) stages but computes nothing
     if (wave_live) {
-    float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
     if constexpr (sizeof(T) == 4) {
       // Full far bricks first (all 8 cells, no screening possible), then the
       // rest (missing cells or possibly screened pairs) in a second pass.
@@ -1122,10 +1126,12 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           pair_fields(lds, PU, e, f, ri, dx, dy, dz, bE, bB);
         }
       }
-      if (!FP) {
+      if (!FP && (++n_blk & 1) == 0) {
         for (int a = 0; a < 3; ++a) {
           two_sum_acc(sE[a], cE[a], bE[a]);
           two_sum_acc(sB[a], cB[a], bB[a]);
+          bE[a] = 0.f;
+          bB[a] = 0.f;
         }
       }
     } else {
@@ -1179,6 +1185,13 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     more = next;
   }
 
+  if constexpr (sizeof(T) == 4) {
+    if (!FP)
+      for (int a = 0; a < 3; ++a) {
+        two_sum_acc(sE[a], cE[a], bE[a]);
+        two_sum_acc(sB[a], cB[a], bB[a]);
+      }
+  }
   if (!valid) return;
   const long long n_obs = (long long)p.obs.n[0] * p.obs.n[1] * p.obs.n[2];
   const long long o = (long long)ix + (long long)p.obs.n[0] * ((long long)iy + (long long)p.obs.n[1] * iz);
