@@ -760,6 +760,9 @@ struct FpAcc {
   }
 };
 
+// Table entries of live bricks waiting for their round (a power of two).
+constexpr int kBrickRing = 64;
+
 // Launch shape: WZ = 1 (8x8x4 tiles, 256 threads) or 2 (8x8x8, 512 threads);
 // W = slots staged per cell (32, 64 or 128) -- the longer the window, the
 // fewer bricks fit a round in the same LDS.
@@ -783,10 +786,9 @@ struct FastShape {
 template <typename T, int WZ, bool FP, int IDX, int W, class PP>
 __device__ __forceinline__ void pair_body(const PP& p, int bid,
                                           float4 (&lds)[FastShape<T, WZ, W>::NPL * FastShape<T, WZ, W>::PU],
-                                          int4 (&tab_i)[2][FastShape<T, WZ, W>::G],
-                                          float4 (&tab_f)[2][FastShape<T, WZ, W>::G],
-                                          double (&tab_c)[2][FastShape<T, WZ, W>::G][6],
-                                          double (&thr)[FastShape<T, WZ, W>::THR], int (&qs)[2][1]) {
+                                          int4 (&tab_i)[kBrickRing], float4 (&tab_f)[kBrickRing],
+                                          double (&tab_c)[kBrickRing][6],
+                                          double (&thr)[FastShape<T, WZ, W>::THR], int (&qs)[2]) {
   using Raw = typename RawOf<T>::type;
   constexpr int G = FastShape<T, WZ, W>::G;
   constexpr int kThreads = FastShape<T, WZ, W>::KT;
@@ -836,14 +838,15 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   FpAcc fpa;
   Raw raw[NRAW];
 
-  // Next round's table: the first G bricks at or after `cursor` that are
-  // not dead for this tile, among the next 64 (dead bricks -- every pair
-  // before the oldest slice -- are skipped instead of occupying round
-  // slots).  Wavefront 0 tests the 64 bricks, one per lane; slots it does
-  // not fill are marked dead, and qs[buf][0] receives the cursor after the
-  // last brick taken (after all 64 when fewer than G were live: the round
-  // is then short or empty).
-  auto make_table = [&](int cursor, int buf) {
+  // Live bricks wait in a ring of kBrickRing table entries (logical
+  // positions, taken modulo the ring size): a round uses the next G of
+  // them.  Wavefront 0 refills the ring when fewer than G wait for the
+  // next round: it tests the 64 bricks from `cursor` on, one per lane, and
+  // appends the live ones (dead bricks -- every pair before the oldest
+  // slice -- take no round slot), as many as there is room for behind
+  // `keep` (the oldest entry still in use).  qs receives the new tail and
+  // the cursor after the last brick taken.
+  auto refill = [&](int keep, int tail, int cursor) {
     if (t < 64) {
       int4 ti;
       float4 tf;
@@ -852,19 +855,27 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       const bool live = !(ti.z & 1);
       const unsigned long long m = __ballot(live);
       const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-      if (live && rank < G) {
-        tab_i[buf][rank] = ti;
-        tab_f[buf][rank] = tf;
-        for (int q = 0; q < 6; ++q) tab_c[buf][rank][q] = cc[q];
-      }
       const int got = (int)__popcll(m);
-      if (t >= got && t < G) tab_i[buf][t] = make_int4(0, -1, 1, 0);
-      const unsigned long long last = __ballot(live && rank == G - 1);
-      if (t == 0) qs[buf][0] = min(got >= G ? cursor + (int)__builtin_ctzll(last) + 1 : cursor + 64, b_end);
+      const int take = min(got, kBrickRing - (tail - keep));
+      if (live && rank < take) {
+        const int q = (tail + rank) & (kBrickRing - 1);
+        tab_i[q] = ti;
+        tab_f[q] = tf;
+        for (int k = 0; k < 6; ++k) tab_c[q][k] = cc[k];
+      }
+      const unsigned long long last = __ballot(live && rank == take - 1);
+      if (t == 0) {
+        qs[0] = tail + take;
+        qs[1] = min(take < got && last != 0ull ? cursor + (int)__builtin_ctzll(last) + 1 : cursor + 64, b_end);
+      }
     }
   };
-  auto load_round = [&](int buf) {
-    const int4 ti = tab_i[buf][sj];
+  // the round's brick slot j: entry pos + j when j < n, else a dead entry
+  auto slot_entry = [&](int pos, int n, int j) {
+    return j < n ? tab_i[(pos + j) & (kBrickRing - 1)] : make_int4(0, -1, 1, 0);
+  };
+  auto load_round = [&](int pos, int n) {
+    const int4 ti = slot_entry(pos, n, sj);
     const int k0 = ti.x + sq * EPT;
     if (p.ring_bytes_rs != 0u) {
       // Buffer addressing over the ring: 32-bit offsets stepped slot by
@@ -911,8 +922,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         load_raw(ring, p, k0 - 1 + r, ti.w, sc, raw[r]);
     }
   };
-  auto write_round = [&](int buf) {
-    const int4 ti = tab_i[buf][sj];
+  auto write_round = [&](int pos, int n) {
+    const int4 ti = slot_entry(pos, n, sj);
     if (ti.z & 1) return;
     if (p.stencil & kStencilSlope) {
 #pragma unroll
@@ -927,13 +938,14 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
                        raw[e + 2], inv_dt);
   };
 
-  int buf = 0;
-  int cursor = b_begin;
+  int cursor = b_begin, tail = 0, pos = 0, cnt = 0;
   if (cursor < b_end) {
-    make_table(cursor, 0);
+    refill(0, 0, cursor);
     __syncthreads();
-    cursor = qs[0][0];
-    load_round(0);
+    tail = qs[0];
+    cursor = qs[1];
+    cnt = min(G, tail);
+    load_round(0, cnt);
   }
   // Source-cell index of a brick's first cell (fingerprints only).
   auto brick_s_base = [&](int b) {
@@ -946,21 +958,25 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     return s_base + (c & 1) + p.src.n[0] * (((c >> 1) & 1) + p.src.n[1] * (c >> 2));
   };
 
-  // rounds continue while bricks remain: the round in `buf` was filled
-  // from bricks before `cursor`; the next one is probed from `cursor`
+  // rounds continue while bricks remain: the round uses ring entries
+  // pos .. pos + cnt - 1; bricks from `cursor` on are not yet tested
   // FP32 block sums of two rounds (up to 64 pairs per lane), then an
   // error-free two-sum into the running totals
   float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
   int n_blk = 0;
   for (bool more = b_begin < b_end; more;) {
-    write_round(buf);
-    const bool next = cursor < b_end;
-    if (next) make_table(cursor, buf ^ 1);
+    write_round(pos, cnt);
+    const int npos = pos + cnt;
+    const bool probe = tail - npos < G && cursor < b_end;
+    if (probe) refill(pos, tail, cursor);
     __syncthreads();
-    if (next) {
-      cursor = qs[buf ^ 1][0];
-      load_round(buf ^ 1);
+    if (probe) {
+      tail = qs[0];
+      cursor = qs[1];
     }
+    const int ncnt = min(G, tail - npos);
+    const bool next = ncnt > 0 || cursor < b_end;
+    if (ncnt > 0) load_round(npos, ncnt);
 
     // a wavefront whose 4x4x4 block lies wholly outside the observation
     // grid (tile padding) stages but computes nothing
@@ -970,19 +986,20 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       // rest (missing cells or possibly screened pairs) in a second pass.
       unsigned slow = 0;
 #pragma unroll 1
-      for (int j = 0; j < G; ++j) {
-        const int tz = __builtin_amdgcn_readfirstlane(tab_i[buf][j].z);
+      for (int j = 0; j < cnt; ++j) {
+        const int q = (pos + j) & (kBrickRing - 1);
+        const int tz = __builtin_amdgcn_readfirstlane(tab_i[q].z);
         if (tz & 1) continue;
         if ((tz & 0xff02) != 0xff00) {
           slow |= 1u << j;
           continue;
         }
-        const int4 ti = tab_i[buf][j];
+        const int4 ti = tab_i[q];
         const int off = p.a_i - ti.x;  // window slot of floor position m: m + off
         const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
         const int mlo = -off;
-        const double* bc = tab_c[buf][j];
-        const float4 tf = tab_f[buf][j];
+        const double* bc = tab_c[q];
+        const float4 tf = tab_f[q];
         const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
         const float d1x = d0x - hsx, d1y = d0y - hsy, d1z = d0z - hsz;
         const float x2[2] = {d0x * d0x, d1x * d1x};
@@ -1091,14 +1108,15 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
 #pragma unroll 1
       for (int j = 0; slow != 0u; ++j, slow >>= 1) {
         if (!(slow & 1u)) continue;
-        const int4 ti = tab_i[buf][j];
+        const int q = (pos + j) & (kBrickRing - 1);
+        const int4 ti = tab_i[q];
         const int lo = ti.x;
         const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;
         const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
         const int mlo = -off, mhi = hiw - off;
-        const double* bc = tab_c[buf][j];
-        const float4 tf = tab_f[buf][j];
+        const double* bc = tab_c[q];
+        const float4 tf = tab_f[q];
         const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
         const float d1x = d0x - hsx, d1y = d0y - hsy, d1z = d0z - hsz;
         const int s_base = FP ? brick_s_base(ti.w) : 0;
@@ -1135,15 +1153,16 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         }
       }
     } else {
-      for (int j = 0; j < G; ++j) {
-        const int4 ti = tab_i[buf][j];
+      for (int j = 0; j < cnt; ++j) {
+        const int q = (pos + j) & (kBrickRing - 1);
+        const int4 ti = tab_i[q];
         if (ti.z & 1) continue;
         const int lo = ti.x;
         const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;
         const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
         const int mlo = -off, mhi = hiw - off;
-        const double* bc = tab_c[buf][j];
+        const double* bc = tab_c[q];
         const int s_base = FP ? brick_s_base(ti.w) : 0;
         const bool fast = (ti.z & 0xff02) == 0xff00;
         const double dx[2] = {rox - bc[0], rox - bc[1]};
@@ -1181,7 +1200,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     }
     }
     __syncthreads();
-    buf ^= 1;
+    pos = npos;
+    cnt = ncnt;
     more = next;
   }
 
@@ -1234,11 +1254,11 @@ template <typename T, int WZ, bool FP, int IDX, int W>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
   using S = FastShape<T, WZ, W>;
   __shared__ float4 lds[S::NPL * S::PU];
-  __shared__ int4 tab_i[2][S::G];
-  __shared__ float4 tab_f[2][S::G];
-  __shared__ double tab_c[2][S::G][6];
+  __shared__ int4 tab_i[kBrickRing];
+  __shared__ float4 tab_f[kBrickRing];
+  __shared__ double tab_c[kBrickRing][6];
   __shared__ double thr[S::THR];
-  __shared__ int qs[2][1];
+  __shared__ int qs[2];
   pair_body<T, WZ, FP, IDX, W>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab_i, tab_f, tab_c, thr, qs);
 }
 
@@ -1249,11 +1269,11 @@ template <typename T, int WZ, int IDX>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_persistent(BatchDevice bd) {
   using S = FastShape<T, WZ, 32>;
   __shared__ float4 lds[S::NPL * S::PU];
-  __shared__ int4 tab_i[2][S::G];
-  __shared__ float4 tab_f[2][S::G];
-  __shared__ double tab_c[2][S::G][6];
+  __shared__ int4 tab_i[kBrickRing];
+  __shared__ float4 tab_f[kBrickRing];
+  __shared__ double tab_c[kBrickRing][6];
   __shared__ double thr[S::THR];
-  __shared__ int qs[2][1];
+  __shared__ int qs[2];
   __shared__ int cur;
   const int n_items = bd.counts[0];
   for (;;) {
