@@ -304,6 +304,8 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   p.margin = 1e-7;
   p.near_slack = 1e-12;
   p.pref = (src->spacing[0] * src->spacing[1] * src->spacing[2]) / (4.0 * M_PI);
+  // the FP32 kernels sum in units of c dt: every term carries (1/(c dt))^2
+  if (r.precision == JEFI_PREC_F32_COMP) p.pref *= ts.inv_cdt * ts.inv_cdt;
   p.n_splits = 1;
   p.bricks_per_split = p.n_bricks;
   p.n_wg = p.n_tiles;
@@ -326,18 +328,21 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   }
   const double rmax = std::sqrt(rmax2), diam_t = std::sqrt(dt2), diam_b = std::sqrt(db2);
   // FP32 index guard: a bound on |u32 - u64| for the FP32 sequence of the
-  // pair kernels, with u = 2^-24 the FP32 unit roundoff:
+  // pair kernels, which works in units of c dt, with u = 2^-24 the FP32
+  // unit roundoff (lengths below in the caller's units):
   //  - coordinates relative to the tile's first point, brick corner, cell
-  //    offset (three roundings deep): |d32 - d| <= u (3R + 2 D_tile + 3 h);
+  //    offset, each scaled by 1/(c dt) in FP64 and rounded once (three
+  //    roundings deep): |d32 - d| <= u (3R + 2 D_tile + 3 h);
   //  - r2 = x^2 + (y^2 + z^2): 3u relative, i.e. 1.5u on R; v_rsq_f32 taken
-  //    as 2 ulp (4u); R = r2 * ri one more rounding: 6.5u relative on R;
-  //  - u = fma(-R, 1/(c dt), a_f) with both constants rounded to FP32: u on
-  //    1/(c dt), u on a_f, u on the result.
+  //    as 2 ulp (4u): 5.5u relative on R = r2 * ri, which the FMA below
+  //    does not round; 1u more covers the FP64 scaling products;
+  //  - u = fma(-r2, ri, a_f) with a_f rounded to FP32: u on a_f, u on the
+  //    result.
   // The band used is 1.25x that bound; a fractional part inside it sends
   // the pair through the canonical FP64 decision.
   const double eps = std::ldexp(1.0, -24);
   const double e_coord = eps * (3.0 * rmax + 2.0 * diam_t + 3.0 * std::sqrt(hsd2));
-  const double e_R = e_coord + 7.5 * eps * rmax;
+  const double e_R = e_coord + 6.5 * eps * rmax;
   const double umax = ts.inv_cdt * rmax + 2.0;
   const double e_u = ts.inv_cdt * e_R + eps * (umax + 1.0);
   double g = 1.25 * e_u + 1e-7;

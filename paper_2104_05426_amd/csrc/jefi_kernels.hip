@@ -107,13 +107,12 @@ __device__ __forceinline__ float r2_f32(float dx, float dy, float dz) {
 }
 
 template <class Canon>
-__device__ __forceinline__ void index_f32(float dx, float dy, float dz, float af, float icdt,
-                                          float halfg, Canon canon_fn, float& m, float& f,
-                                          float& ri) {
+__device__ __forceinline__ void index_f32(float dx, float dy, float dz, float af, float halfg,
+                                          Canon canon_fn, float& m, float& f, float& ri) {
+  // separations in units of c dt: R = r2 / sqrt(r2) lands in slice units
   float r2 = r2_f32(dx, dy, dz);
   ri = __builtin_amdgcn_rsqf(r2);
-  float R = r2 * ri;
-  float u = __builtin_fmaf(-R, icdt, af);
+  float u = __builtin_fmaf(-r2, ri, af);
   float fl = __builtin_floorf(u);
   float fr = u - fl;
   // NaN (a separation below FP32 resolution) also takes the FP64 decision
@@ -314,7 +313,7 @@ __device__ __forceinline__ TileGeom tile_geom(const PP& p, int tile) {
 // must be clamped to the window's slot -2 entry: zero, or the held slice 0
 // with zero derivative), bits 8..15 = valid cells;
 // tf = brick corner relative to
-// the tile reference in FP32; cc = canonical x0, x1, y0, y1, z0, z1.
+// the tile reference in FP32, in units of c dt; cc = canonical x0, x1, y0, y1, z0, z1.
 template <class PP>
 __device__ __forceinline__ void brick_info(const PP& p, const TileGeom& g, int b, int b_end,
                                            int4& ti, float4& tf, double cc[6]) {
@@ -364,7 +363,8 @@ __device__ __forceinline__ void brick_info(const PP& p, const TileGeom& g, int b
   // cells with cx = 1 (cy = 1, cz = 1) exist when the brick has two layers in x (y, z)
   const int vmask = (i1 > i0 ? 0xff : 0x55) & (j1 > j0 ? 0xff : 0x33) & (k1 > k0 ? 0xff : 0x0f);
   ti = make_int4(max(jlo, -2), jhi, (dead ? 1 : 0) | (near ? 2 : 0) | (jlo < -2 ? 4 : 0) | (vmask << 8), b);
-  tf = make_float4((float)(cc[0] - g.refx), (float)(cc[2] - g.refy), (float)(cc[4] - g.refz), 0.f);
+  tf = make_float4((float)((cc[0] - g.refx) * p.inv_cdt), (float)((cc[2] - g.refy) * p.inv_cdt),
+                   (float)((cc[4] - g.refz) * p.inv_cdt), 0.f);
 }
 
 template <typename T, int G, bool FP, bool MULTI>
@@ -406,10 +406,13 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
   double dE[3] = {0.0, 0.0, 0.0}, dB[3] = {0.0, 0.0, 0.0};
   unsigned long long n_live = 0, sum_k = 0, sum_kw = 0, n_scr = 0;
 
-  const float xo = (float)(rox - refx), yo = (float)(roy - refy), zo = (float)(roz - refz);
-  const float hsx = (float)p.src.h[0], hsy = (float)p.src.h[1], hsz = (float)p.src.h[2];
-  const float af32 = (float)p.a_f, icdt32 = (float)p.inv_cdt, halfg = 0.5f - p.guard;
-  const T inv_dt = (T)p.inv_dt;
+  // FP32 arithmetic works in units of c dt (lengths scaled by 1/(c dt), time
+  // derivatives by dt); the prefactor of the FP32 plan scales the sums back
+  const double ls = p.inv_cdt;
+  const float xo = (float)((rox - refx) * ls), yo = (float)((roy - refy) * ls), zo = (float)((roz - refz) * ls);
+  const float hsx = (float)(p.src.h[0] * ls), hsy = (float)(p.src.h[1] * ls), hsz = (float)(p.src.h[2] * ls);
+  const float af32 = (float)p.a_f, halfg = 0.5f - p.guard;
+  const T inv_dt = sizeof(T) == 4 ? (T)(p.inv_dt / p.inv_cdt) : (T)p.inv_dt;
 
   for (int rb = b_begin; rb < b_end; rb += G) {
     __syncthreads();  // the previous round's readers are done with LDS and the table
@@ -502,7 +505,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
             const float dy = cy ? d0y - hsy : d0y;
             const float dz = cz ? d0z - hsz : d0z;
             float m, f, ri;
-            index_f32(dx, dy, dz, af32, icdt32, halfg,
+            index_f32(dx, dy, dz, af32, halfg,
                       [&]() {
                         return canon_u(rox - tab_c[j][cx], roy - tab_c[j][2 + cy],
                                        roz - tab_c[j][4 + cz], p.a_f, p.inv_cdt);
@@ -817,10 +820,14 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   const double rox = canon(p.obs.o[0], cix, p.obs.h[0]);
   const double roy = canon(p.obs.o[1], ciy, p.obs.h[1]);
   const double roz = canon(p.obs.o[2], ciz, p.obs.h[2]);
-  const float xo = (float)(rox - tg.refx), yo = (float)(roy - tg.refy), zo = (float)(roz - tg.refz);
-  const float hsx = (float)p.src.h[0], hsy = (float)p.src.h[1], hsz = (float)p.src.h[2];
-  const float af32 = (float)p.a_f, icdt32 = (float)p.inv_cdt, halfg = 0.5f - p.guard;
-  const T inv_dt = (T)p.inv_dt;
+  // FP32 arithmetic works in units of c dt (lengths scaled by 1/(c dt), time
+  // derivatives by dt); the prefactor of the FP32 plan scales the sums back
+  const double ls = p.inv_cdt;
+  const float xo = (float)((rox - tg.refx) * ls), yo = (float)((roy - tg.refy) * ls),
+              zo = (float)((roz - tg.refz) * ls);
+  const float hsx = (float)(p.src.h[0] * ls), hsy = (float)(p.src.h[1] * ls), hsz = (float)(p.src.h[2] * ls);
+  const float af32 = (float)p.a_f, halfg = 0.5f - p.guard;
+  const T inv_dt = sizeof(T) == 4 ? (T)(p.inv_dt / p.inv_cdt) : (T)p.inv_dt;
   const T* ring = (const T*)p.ring;
   // threshold of floor position N at thr_at[N]; N stays in the table's range
   const double* thr_at = &thr[0] - p.thr_lo;
@@ -942,8 +949,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   if (cursor < b_end) {
     refill(0, 0, cursor);
     __syncthreads();
-    tail = qs[0];
-    cursor = qs[1];
+    tail = __builtin_amdgcn_readfirstlane(qs[0]);  // uniform: keeps ring positions scalar
+    cursor = __builtin_amdgcn_readfirstlane(qs[1]);
     cnt = min(G, tail);
     load_round(0, cnt);
   }
@@ -971,8 +978,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     if (probe) refill(pos, tail, cursor);
     __syncthreads();
     if (probe) {
-      tail = qs[0];
-      cursor = qs[1];
+      tail = __builtin_amdgcn_readfirstlane(qs[0]);  // uniform: keeps ring positions scalar
+      cursor = __builtin_amdgcn_readfirstlane(qs[1]);
     }
     const int ncnt = min(G, tail - npos);
     const bool next = ncnt > 0 || cursor < b_end;
@@ -1012,7 +1019,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         for (int c = 0; c < 8; ++c) {
           const float r2 = x2[c & 1] + yz[c >> 1];
           ri[c] = __builtin_amdgcn_rsqf(r2);
-          uu[c] = __builtin_fmaf(-(r2 * ri[c]), icdt32, af32);
+          uu[c] = __builtin_fmaf(-r2, ri[c], af32);
         }
         if constexpr (IDX == 1) {
           // Every pair: N = nearest integer to u32, then floor(u64) = N when
@@ -1132,7 +1139,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           }
           const float dx = cx ? d1x : d0x, dy = cy ? d1y : d0y, dz = cz ? d1z : d0z;
           float mf, f, ri;
-          index_f32(dx, dy, dz, af32, icdt32, halfg,
+          index_f32(dx, dy, dz, af32, halfg,
                     [&]() { return canon_u(rox - bc[cx], roy - bc[2 + cy], roz - bc[4 + cz], p.a_f, p.inv_cdt); },
                     mf, f, ri);
           const int mm = (int)mf;
@@ -1452,18 +1459,20 @@ __global__ void dump_kernel(DumpParams p) {
         const double refx = canon(p.obs.o[0], tx0, p.obs.h[0]);
         const double refy = canon(p.obs.o[1], ty0, p.obs.h[1]);
         const double refz = canon(p.obs.o[2], tz0, p.obs.h[2]);
-        const float xo = (float)(rox - refx), yo = (float)(roy - refy), zo = (float)(roz - refz);
+        const double ls = p.inv_cdt;
+        const float xo = (float)((rox - refx) * ls), yo = (float)((roy - refy) * ls),
+                    zo = (float)((roz - refz) * ls);
         const double bxc = canon(p.src.o[0], si & ~1, p.src.h[0]);
         const double byc = canon(p.src.o[1], sj & ~1, p.src.h[1]);
         const double bzc = canon(p.src.o[2], sk & ~1, p.src.h[2]);
-        const float d0x = xo - (float)(bxc - refx);
-        const float d0y = yo - (float)(byc - refy);
-        const float d0z = zo - (float)(bzc - refz);
-        const float dx = (si & 1) ? d0x - (float)p.src.h[0] : d0x;
-        const float dy = (sj & 1) ? d0y - (float)p.src.h[1] : d0y;
-        const float dz = (sk & 1) ? d0z - (float)p.src.h[2] : d0z;
+        const float d0x = xo - (float)((bxc - refx) * ls);
+        const float d0y = yo - (float)((byc - refy) * ls);
+        const float d0z = zo - (float)((bzc - refz) * ls);
+        const float dx = (si & 1) ? d0x - (float)(p.src.h[0] * ls) : d0x;
+        const float dy = (sj & 1) ? d0y - (float)(p.src.h[1] * ls) : d0y;
+        const float dz = (sk & 1) ? d0z - (float)(p.src.h[2] * ls) : d0z;
         float m, f, ri;
-        index_f32(dx, dy, dz, (float)p.a_f, (float)p.inv_cdt, 0.5f - p.guard,
+        index_f32(dx, dy, dz, (float)p.a_f, 0.5f - p.guard,
                   [&]() { return canon_u(rox - rsx, roy - rsy, roz - rsz, p.a_f, p.inv_cdt); }, m, f,
                   ri);
         k = p.a_i + (int)m;
