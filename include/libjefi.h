@@ -67,7 +67,10 @@ typedef enum { JEFI_F32 = 0, JEFI_F64 = 1 } jefi_dtype;
 /* JEFI_PREC_F64: all pair arithmetic in FP64 (needs an F64 history).
  * JEFI_PREC_F32_COMP: FP32 pair arithmetic (rsqrt, FMA) with compensated
  * accumulation, FP64 for the slice index near slice boundaries and for the
- * final per-point reduction (needs an F32 history). */
+ * final per-point reduction (needs an F32 history).  The FP32 arithmetic
+ * measures lengths in units of c*dt, so separations must stay well inside
+ * the FP32 range in those units (roughly 1e-18 to 1e18 c*dt; squares are
+ * formed). */
 typedef enum { JEFI_PREC_F64 = 0, JEFI_PREC_F32_COMP = 1 } jefi_precision;
 
 /* Uniform grid: n cells per axis (n >= 1 each, or all three 0 for an empty
