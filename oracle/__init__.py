@@ -26,6 +26,7 @@ _LIB = _DEFAULT_LIB
 SCREENED = -(2 ** 31)
 STENCIL_SLOPE = 1  # time derivative = slope of the linear interpolant
 STENCIL_HOLD = 2   # history before the oldest slice = the oldest slice
+STENCIL_CUBIC = 4  # cubic through slices k-2 .. k+1 (not with STENCIL_SLOPE)
 
 
 class _Grid(C.Structure):
@@ -121,7 +122,9 @@ def eval_fields(src, obs, hist: np.ndarray, dt: float, t: float, t0: float = 0.0
     spacing); ``sel`` = observation linear indices (default all).
     ``stencil``: reading of the time stencil, bit 0 = derivative as the
     slope of the interpolant (``STENCIL_SLOPE``), bit 1 = history before
-    the oldest slice held at its values (``STENCIL_HOLD``); 0 = the
+    the oldest slice held at its values (``STENCIL_HOLD``), bit 2 = cubic
+    time interpolation through slices k-2 .. k+1 (``STENCIL_CUBIC``, not
+    with bit 0); 0 = the
     interpolated backward difference and a zero past."""
     lib = _load()
     h = np.ascontiguousarray(hist, dtype=np.float64)

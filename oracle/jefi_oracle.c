@@ -31,8 +31,15 @@
  *     interpolated backward difference;
  *   - bit 1: slices before the oldest stored one hold the oldest slice's
  *     values (sources constant before the retained window), so h_(-1) = h_0
- *     inside D_0 and no pair is ever wholly in an empty past.
- * Neither changes the slice index k or the screening decision.
+ *     inside D_0 and no pair is ever wholly in an empty past;
+ *   - bit 2: cubic time interpolation: value and time derivative from the
+ *     cubic through slices k-2, k-1, k, k+1 (the Lagrange polynomial on
+ *     those four nodes, evaluated at position f past slice k, and its
+ *     derivative divided by dt).  Its nodes end at k+1, so it reads no slice
+ *     the linear stencil does not reach at the top, and a pair whose k+1
+ *     lies before the oldest slice still contributes nothing.  It cannot be
+ *     combined with bit 0.
+ * None of them changes the slice index k or the screening decision.
  *   - the slice index is k = a_i + floor(u), u = a_f - R*inv_cdt with the
  *     host split a = (t - t0)/dt - s_old = a_i + a_f, all in FP64 with no
  *     contraction; the interpolation weight is f = u - floor(u) and slice
@@ -161,6 +168,45 @@ static double orc_h(const double* hist, int64_t ns, int64_t j, int ch, int64_t s
   return hist[(j * 4 + ch) * ns + s];
 }
 
+/* Cubic time interpolation (stencil bit 2): the Lagrange polynomial through
+ * slices k-2 .. k+1, placed at nodes x = -2 .. 1, evaluated at x = f; val =
+ * sum_i w_i h_(k+i) and der = sum_i w_i' h_(k+i) / dt with
+ *   w_i(f)  = prod_(j != i) (f - x_j) / (x_i - x_j),
+ *   w_i'(f) = sum_(m != i) [1 / (x_i - x_m)] prod_(j != i, m) (f - x_j) / (x_i - x_j). */
+static void orc_cubic(const double* hist, int64_t ns, int64_t k, double f, double inv_dt, int64_t s,
+                      int hold, double val[4], double der[4]) {
+  static const double x[4] = {-2.0, -1.0, 0.0, 1.0};
+  double w[4], dw[4];
+  for (int i = 0; i < 4; ++i) {
+    double p = 1.0, dp = 0.0;
+    for (int j = 0; j < 4; ++j) {
+      if (j == i) continue;
+      p *= (f - x[j]) / (x[i] - x[j]);
+    }
+    for (int m = 0; m < 4; ++m) {
+      if (m == i) continue;
+      double q = 1.0 / (x[i] - x[m]);
+      for (int j = 0; j < 4; ++j) {
+        if (j == i || j == m) continue;
+        q *= (f - x[j]) / (x[i] - x[j]);
+      }
+      dp += q;
+    }
+    w[i] = p;
+    dw[i] = dp;
+  }
+  for (int ch = 0; ch < 4; ++ch) {
+    double v = 0.0, d = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      double h = orc_h(hist, ns, k - 2 + i, ch, s, hold);
+      v += w[i] * h;
+      d += dw[i] * h;
+    }
+    val[ch] = v;
+    der[ch] = d * inv_dt;
+  }
+}
+
 /* ---- field evaluation ----------------------------------------------- */
 
 /* Evaluate E and B at the selected observation points.
@@ -177,8 +223,8 @@ int orc_eval(const orc_grid* src, const orc_grid* obs, const double* hist, int32
              const int64_t* sel, int64_t n_sel, double* E, double* B, int32_t threads,
              int32_t stencil) {
   if (!src || !obs || !hist || !E || !B || !delta) return -1;
-  if (stencil < 0 || stencil > 3) return -1;
-  const int slope = (stencil & 1) != 0, hold = (stencil & 2) != 0;
+  if (stencil < 0 || stencil > 7 || (stencil & 5) == 5) return -1;
+  const int slope = (stencil & 1) != 0, hold = (stencil & 2) != 0, cubic = (stencil & 4) != 0;
   if (!orc_grid_ok(src) || !orc_grid_ok(obs)) return -1;
   orc_time tm;
   int rc = orc_time_prelude(t, t0, dt, newest, nt, c, &tm);
@@ -206,8 +252,11 @@ int orc_eval(const orc_grid* src, const orc_grid* obs, const double* hist, int32
       orc_centre(src, s, rs);
       if (orc_pair(ro, rs, delta, &tm, d, &R, &k, &f)) continue;
       if (k < -1 && !hold) continue; /* the whole stencil lies before the oldest slice */
-      if ((f != 0.0 || slope) && k + 1 > (int64_t)nt - 1) { bad |= 2; continue; }
+      if ((f != 0.0 || slope || cubic) && k + 1 > (int64_t)nt - 1) { bad |= 2; continue; }
       double val[4], der[4];
+      if (cubic) {
+        orc_cubic(hist, ns, k, f, inv_dt, s, hold, val, der);
+      } else {
       for (int ch = 0; ch < 4; ++ch) {
         double h0 = orc_h(hist, ns, k, ch, s, hold);
         double hm = orc_h(hist, ns, k - 1, ch, s, hold);
@@ -224,6 +273,7 @@ int orc_eval(const orc_grid* src, const orc_grid* obs, const double* hist, int32
         if (slope) w = (orc_h(hist, ns, k + 1, ch, s, hold) - h0) * inv_dt;
         val[ch] = v;
         der[ch] = w;
+      }
       }
       double rho = val[0], rhod = der[0];
       const double* J = &val[1];

@@ -8,9 +8,11 @@ it shares neither code nor summation scheme with the C oracle.  The same
 readings apply: linear interpolation in time between slices, backward
 differences interpolated the same way, zero history before the oldest slice,
 the slice index from the FP64 split a = a_i + a_f, and the cube screening.
-The two alternative time-stencil readings (derivative as the slope of the
-interpolant; history before the oldest slice held at its values) are
-selected by the same ``stencil`` bits as the C oracle.
+The alternative time-stencil readings (derivative as the slope of the
+interpolant; history before the oldest slice held at its values; cubic time
+interpolation through slices k-2 .. k+1) are selected by the same
+``stencil`` bits as the C oracle.  The cubic is written here in Newton's
+forward-difference form, the C oracle uses Lagrange weights.
 
 Cost is O(n_obs * n_src * 4) Python operations: keep n_obs * n_src <= ~3e5.
 """
@@ -64,9 +66,12 @@ def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
                 sel: Sequence[int] | None = None, stencil: int = 0):
     """E, B as lists [3][n_out] of floats.  ``hist[j][ch][s]`` with j = 0
     the oldest of nt slices.  ``stencil`` bit 0: slope derivative; bit 1:
-    held past."""
+    held past; bit 2: cubic."""
     slope = bool(stencil & 1)
     hold = bool(stencil & 2)
+    cubic = bool(stencil & 4)
+    if slope and cubic:
+        raise ValueError("the slope and cubic readings exclude each other")
     nt = len(hist)
     ai, af, inv_cdt = time_split(t, t0, dt, newest, nt, c)
     ns = src.n[0] * src.n[1] * src.n[2]
@@ -97,7 +102,23 @@ def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
             # linear interpolations between slices k and k+1
             val = []
             der = []
-            for ch in range(4):
+            if cubic:
+                if k + 1 > nt - 1:
+                    raise ValueError("stencil reaches past the newest slice")
+                for ch in range(4):
+                    # Newton form on nodes -2, -1, 0, 1 with x = f + 2 steps from
+                    # the first node: p = y0 + x D1 + x(x-1) D2/2 + x(x-1)(x-2) D3/6
+                    y = [H(k - 2 + i, ch, s) for i in range(4)]
+                    d1 = y[1] - y[0]
+                    d2 = y[2] - 2.0 * y[1] + y[0]
+                    d3 = y[3] - 3.0 * y[2] + 3.0 * y[1] - y[0]
+                    x = f + 2.0
+                    val.append(math.fsum([y[0], x * d1, x * (x - 1.0) * d2 / 2.0,
+                                          x * (x - 1.0) * (x - 2.0) * d3 / 6.0]))
+                    dp = math.fsum([d1, (2.0 * x - 1.0) * d2 / 2.0,
+                                    (3.0 * x * x - 6.0 * x + 2.0) * d3 / 6.0])
+                    der.append(dp / dt)
+            for ch in range(4 if not cubic else 0):
                 lo = H(k, ch, s)
                 dlo = (lo - H(k - 1, ch, s)) / dt
                 if f != 0.0:

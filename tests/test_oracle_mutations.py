@@ -30,6 +30,12 @@ MUTATIONS = {
     "slope reading uses the backward difference": ("if (slope) w = (orc_h(hist, ns, k + 1, ch, s, hold) - h0) * inv_dt;",
                                                    "if (slope) w = (h0 - hm) * inv_dt;"),
     "held past still culls old stencils": ("if (k < -1 && !hold) continue;", "if (k < -1) continue;"),
+    "cubic on nodes k-1 .. k+2": ("static const double x[4] = {-2.0, -1.0, 0.0, 1.0};\n",
+                                  "static const double x[4] = {-1.0, 0.0, 1.0, 2.0};\n"),
+    "cubic derivative not divided by dt": ("der[ch] = d * inv_dt;", "der[ch] = d;"),
+    "cubic derivative weights unscaled": ("double q = 1.0 / (x[i] - x[m]);", "double q = 1.0;"),
+    "cubic read one slice early": ("double h = orc_h(hist, ns, k - 2 + i, ch, s, hold);",
+                                   "double h = orc_h(hist, ns, k - 3 + i, ch, s, hold);"),
     "held past keeps h(-1) = 0 in D_0": ("double hm = orc_h(hist, ns, k - 1, ch, s, hold);",
                                          "double hm = k - 1 < 0 ? 0.0 : orc_h(hist, ns, k - 1, ch, s, hold);"),
 }
@@ -51,6 +57,9 @@ PIN_CALLS = [
     lambda: pins.test_held_past_linear_history(3),
     pins.test_voxelised_uniform_sphere_is_coulomb_outside,
     pins.test_uniform_charge_and_current_box_match_the_continuum,
+    pins.test_cubic_history_is_reproduced_exactly,
+    pins.test_quartic_history_pins_the_cubic_nodes,
+    lambda: pins.test_switch_on_cubic_reading("k=-1"),
 ]
 
 

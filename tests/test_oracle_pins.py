@@ -220,7 +220,100 @@ def test_switch_on_slope_reading(where):
     assert np.allclose(E[:, 0], E_ref, rtol=1e-12, atol=0)
 
 
-@pytest.mark.parametrize("stencil", [2, 3])
+def _poly_fields(coef_rho, coef_J, stencil, nt=120, dt=0.05):
+    """Oracle E and a closed form for sources polynomial in time (rho and
+    every J component), every stencil inside the stored window; the closed
+    form takes value and derivative of the same polynomial at t_r."""
+    src = _single_cell()
+    obs = _obs_points(n=(4, 3, 3), origin=(0.55, 0.1, -0.2), sp=(0.13, 0.11, 0.07))
+    pr = np.polynomial.Polynomial(coef_rho)
+    pj = [np.polynomial.Polynomial(c) for c in coef_J]
+    hist = _hist_from(lambda t: [pr(t), pj[0](t), pj[1](t), pj[2](t)], nt, 0, dt)
+    t = (nt - 1) * dt - 0.013
+    E, B = oracle.eval_fields(src, obs, hist, dt, t=t, screen=(0, 0, 0), stencil=stencil)
+    d = _centres(obs)
+    R = np.linalg.norm(d, axis=1)
+    tr = t - R
+    return E, B, d, R, tr, pr, pj, dt
+
+
+def test_cubic_history_is_reproduced_exactly():
+    """Cubic time interpolation (stencil bit 2) is exact for sources cubic
+    in time: value and time derivative at t_r are those of the polynomial,
+    so E and B equal the retarded closed forms."""
+    E, B, d, R, tr, pr, pj, _ = _poly_fields([0.3, -0.7, 0.4, 0.25],
+                                             [[0.1, 0.2, -0.3, 0.05], [-0.2, 0.0, 0.1, -0.15],
+                                              [0.4, -0.1, 0.0, 0.2]], oracle.STENCIL_CUBIC)
+    dom = 0.1 * 0.2 * 0.15
+    Jr = np.stack([p(tr) for p in pj], axis=1)
+    Jd = np.stack([p.deriv()(tr) for p in pj], axis=1)
+    E_ref = (dom / FOUR_PI) * (d.T * pr(tr) / R ** 3 + d.T * pr.deriv()(tr) / R ** 2 - Jd.T / R)
+    B_ref = (dom / FOUR_PI) * (np.cross(Jr, d).T / R ** 3 + np.cross(Jd, d).T / R ** 2)
+    assert np.allclose(E, E_ref, rtol=1e-9, atol=1e-13)
+    assert np.allclose(B, B_ref, rtol=1e-9, atol=1e-13)
+    # the linear default is not exact for these sources
+    E_lin, _, _, _, _, _, _, _ = _poly_fields([0.3, -0.7, 0.4, 0.25], [[0.0]] * 3, 0)
+    assert not np.allclose(E_lin, E, rtol=1e-6, atol=0)
+
+
+def test_quartic_history_pins_the_cubic_nodes():
+    """rho = t^4: the cubic through slices k-2 .. k+1 misses it by
+    dt^4 g(f), g(f) = (f+2)(f+1)f(f-1) (the interpolation error of t^4 is
+    exact: its fourth derivative is 24 = 4!), and its derivative by
+    dt^3 g'(f).  Nodes k-1 .. k+2 would give (f+1)f(f-1)(f-2) instead."""
+    E, _, d, R, tr, _, _, dt = _poly_fields([0.0, 0.0, 0.0, 0.0, 1.0], [[0.0]] * 3, oracle.STENCIL_CUBIC)
+    pos = tr / dt
+    f = pos - np.floor(pos)
+    g = (f + 2) * (f + 1) * f * (f - 1)
+    gp = 4 * f ** 3 + 6 * f ** 2 - 2 * f - 2
+    val = tr ** 4 - dt ** 4 * g
+    der = 4 * tr ** 3 - dt ** 3 * gp
+    dom = 0.1 * 0.2 * 0.15
+    E_ref = (dom / FOUR_PI) * (d.T * val / R ** 3 + d.T * der / R ** 2)
+    assert np.allclose(E, E_ref, rtol=1e-10, atol=1e-15)
+    g_alt = (f + 1) * f * (f - 1) * (f - 2)
+    E_alt = (dom / FOUR_PI) * (d.T * (tr ** 4 - dt ** 4 * g_alt) / R ** 3 + d.T * der / R ** 2)
+    assert not np.allclose(E, E_alt, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("where", ["k=-1", "k=-2"])
+def test_switch_on_cubic_reading(where):
+    """Constant rho = h from the oldest slice on, zero before it, cubic
+    reading: at k = -1 the nodes -3 .. 0 carry 0, 0, 0, h, so the value is
+    h (f+2)(f+1)f/6 and the derivative h (3f^2 + 6f + 2)/(6 dt); at k = -2
+    every node lies before the oldest slice and the pair gives exactly 0."""
+    h, dt = 2.5, 0.1
+    nt = 6
+    src = _single_cell(h=(0.1, 0.1, 0.1))
+    t = (nt - 1) * dt
+    target = {"k=-1": -0.037, "k=-2": -0.13}[where]
+    R = t - target
+    obs = Grid((1, 1, 1), (R * 0.6, R * 0.8, 0.0), (0.1, 0.1, 0.1))
+    hist = _hist_from(lambda tt: [h, 0.0, 0.0, 0.0], nt, 0, dt)
+    E, B = oracle.eval_fields(src, obs, hist, dt, t=t, screen=(0, 0, 0), stencil=oracle.STENCIL_CUBIC)
+    if where == "k=-2":
+        assert np.all(E == 0.0) and np.all(B == 0.0)
+        return
+    d = _centres(obs)[0]
+    Rr = float(np.linalg.norm(d))
+    pos = (t - Rr) / dt
+    f = pos - math.floor(pos)
+    val = h * (f + 2) * (f + 1) * f / 6
+    der = h * (3 * f * f + 6 * f + 2) / (6 * dt)
+    E_ref = (1e-3 / FOUR_PI) * (d * val / Rr ** 3 + d * der / Rr ** 2)
+    assert np.allclose(E[:, 0], E_ref, rtol=1e-12, atol=0)
+
+
+def test_slope_and_cubic_readings_exclude_each_other():
+    src = _single_cell()
+    obs = _obs_points()
+    hist = np.zeros((4, 4, 1))
+    for st in (oracle.STENCIL_SLOPE | oracle.STENCIL_CUBIC, 7):
+        with pytest.raises(Exception):
+            oracle.eval_fields(src, obs, hist, 0.05, t=0.15, screen=(0, 0, 0), stencil=st)
+
+
+@pytest.mark.parametrize("stencil", [2, 3, 6])
 def test_held_past_constant_history_is_static_at_any_time(stencil):
     """History held at the oldest slice (stencil bit 1) and constant sources:
     the retarded sources are the constant ones at every t_r, so E and B are
@@ -237,10 +330,12 @@ def test_held_past_constant_history_is_static_at_any_time(stencil):
     dom = 0.1 * 0.2 * 0.15
     E_ref = (q * dom / FOUR_PI) * d.T / R ** 3
     B_ref = (dom / FOUR_PI) * np.cross(J[None, :], d).T / R ** 3
+    # the cubic's weights and their derivatives sum to 1 and 0 only up to rounding
+    rtol = 1e-12 if stencil & oracle.STENCIL_CUBIC else 1e-14
     for t in [(nt - 1) * dt, 0.0, -0.4, -7.0]:
         E, B = oracle.eval_fields(src, obs, hist, dt, t=t, screen=(0, 0, 0), stencil=stencil)
-        assert np.allclose(E, E_ref, rtol=1e-14, atol=0), t
-        assert np.allclose(B, B_ref, rtol=1e-14, atol=1e-18), t
+        assert np.allclose(E, E_ref, rtol=rtol, atol=0), t
+        assert np.allclose(B, B_ref, rtol=rtol, atol=1e-18), t
     E0, B0 = oracle.eval_fields(src, obs, hist, dt, t=-7.0, screen=(0, 0, 0))
     assert np.all(E0 == 0.0) and np.all(B0 == 0.0)
 
@@ -495,7 +590,7 @@ def test_c_oracle_matches_pure_python_on_random_tiny_problems(seed):
     assert np.array_equal(d1, d2)
 
 
-@pytest.mark.parametrize("seed,stencil", [(s, st) for s in range(4) for st in (1, 2, 3)])
+@pytest.mark.parametrize("seed,stencil", [(s, st) for s in range(4) for st in (1, 2, 3, 4, 6)])
 def test_c_oracle_matches_pure_python_stencil_readings(seed, stencil):
     rng = np.random.default_rng(300 + seed)
     src, obs, hist, dt, t, t0, newest, c, screen = _random_problem(rng)
