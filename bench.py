@@ -419,8 +419,9 @@ def run_serve_workload(args):
 def run_stencil_variants(args, p, extra):
     """The same workload under the alternative time-stencil readings (FP32
     path): derivative as the slope of the interpolant, history before the
-    oldest slice held at its values (no pair culled as past), both; rate and
-    parity against the oracle with the same reading on sampled points."""
+    oldest slice held at its values (no pair culled as past), both, and
+    cubic time interpolation; rate and parity against the oracle with the
+    same reading on sampled points."""
     import oracle
     import paper_2104_05426_amd as J
     from oracle.compare import max_rel_l2
@@ -432,7 +433,8 @@ def run_stencil_variants(args, p, extra):
     for name, flag, st in [("slope", J.JEFI_FLAG_DERIV_SLOPE, oracle.STENCIL_SLOPE),
                            ("hold", J.JEFI_FLAG_PAST_HOLD, oracle.STENCIL_HOLD),
                            ("slope+hold", J.JEFI_FLAG_DERIV_SLOPE | J.JEFI_FLAG_PAST_HOLD,
-                            oracle.STENCIL_SLOPE | oracle.STENCIL_HOLD)]:
+                            oracle.STENCIL_SLOPE | oracle.STENCIL_HOLD),
+                           ("cubic", J.JEFI_FLAG_TIME_CUBIC, oracle.STENCIL_CUBIC)]:
         r = run_path(p, extra, "f32", K, W, flags=flag)
         last = r["newest"]
         win = full[last - p.nt + 1:last + 1]

@@ -110,8 +110,10 @@ typedef struct {
   double screen[3];      /* screening half-widths, used when screen_set != 0 */
   int32_t screen_set;    /* 0: half the source spacing per axis (default) */
   int32_t precision;     /* jefi_precision (default JEFI_PREC_F32_COMP) */
-  uint32_t flags;        /* at most one JEFI_FLAG_INDEX_* value, plus JEFI_FLAG_DERIV_SLOPE
-                            and/or JEFI_FLAG_PAST_HOLD; other bits are rejected (EINVAL) */
+  uint32_t flags;        /* at most one JEFI_FLAG_INDEX_* value, at most one of
+                            JEFI_FLAG_DERIV_SLOPE and JEFI_FLAG_TIME_CUBIC, and
+                            JEFI_FLAG_PAST_HOLD; other bits and combinations are
+                            rejected (EINVAL) */
   int32_t tile_config;   /* launch shape: 0 = automatic (autotuned table, else a size
                             heuristic), 1 = 8x8x8 observation tiles (512 threads),
                             2 = 8x8x4 tiles (256 threads) */
@@ -136,18 +138,24 @@ enum {
  * (h_k - h_(k-1))/dt, and the history is zero before the oldest slice of the
  * window (pairs whose stencil lies wholly before it contribute nothing).
  * These flags select the alternatives, in any combination with each other
- * and with an index flag:
+ * (except JEFI_FLAG_DERIV_SLOPE with JEFI_FLAG_TIME_CUBIC) and with an index
+ * flag:
  *   JEFI_FLAG_DERIV_SLOPE: the derivative is the slope of the linear
  *     interpolant on the interval that holds t_r, (h_(k+1) - h_k)/dt.
  *   JEFI_FLAG_PAST_HOLD: before the oldest slice of the window the history
  *     holds that slice's values (sources constant before the window); no
  *     pair is then culled as lying in the past, so every unscreened pair is
  *     computed.
- * Neither changes the slice index k, the screening decision or the
+ *   JEFI_FLAG_TIME_CUBIC: value and time derivative at t_r come from the
+ *     cubic through slices k-2, k-1, k, k+1 (exact for sources cubic in
+ *     time).  Its nodes end at k+1, like the linear stencil's, so the same
+ *     pairs are live and no slice after the newest is read.
+ * None of them changes the slice index k, the screening decision or the
  * fingerprint (jefi_slice_fingerprint, jefi_slice_index_dump). */
 enum {
   JEFI_FLAG_DERIV_SLOPE = 4,
-  JEFI_FLAG_PAST_HOLD = 8
+  JEFI_FLAG_PAST_HOLD = 8,
+  JEFI_FLAG_TIME_CUBIC = 16
 };
 
 const char* jefi_version(void);

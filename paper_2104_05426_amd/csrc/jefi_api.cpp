@@ -132,12 +132,14 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
   if (opt->tile_config < 0 || opt->tile_config > 2)
     return fail(JEFI_EINVAL, "tile_config %d (0 = auto, 1 = 8x8x8, 2 = 8x8x4)", opt->tile_config);
   const unsigned known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE |
-                         JEFI_FLAG_PAST_HOLD;
+                         JEFI_FLAG_PAST_HOLD | JEFI_FLAG_TIME_CUBIC;
   const unsigned idx = opt->flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE);
-  if ((opt->flags & ~known) != 0 || idx == (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE))
+  const unsigned slope_cubic = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
+  if ((opt->flags & ~known) != 0 || idx == (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE) ||
+      (opt->flags & slope_cubic) == slope_cubic)
     return fail(JEFI_EINVAL,
-                "flags 0x%x (at most one JEFI_FLAG_INDEX_* value, plus JEFI_FLAG_DERIV_SLOPE and/or "
-                "JEFI_FLAG_PAST_HOLD)",
+                "flags 0x%x (at most one JEFI_FLAG_INDEX_* value, at most one of JEFI_FLAG_DERIV_SLOPE "
+                "and JEFI_FLAG_TIME_CUBIC, and JEFI_FLAG_PAST_HOLD)",
                 opt->flags);
   r->flags = opt->flags;
   r->c = opt->c;
@@ -295,7 +297,8 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   set_tiles(p, obs, tile_z);
   plan->empty = p.n_tiles == 0 || p.n_bricks == 0;
   p.a_i = ts.a_i <= -2 ? -2 : (int)ts.a_i;
-  p.stencil = ((r.flags & JEFI_FLAG_DERIV_SLOPE) ? kStencilSlope : 0) | (hold ? kStencilHold : 0);
+  p.stencil = ((r.flags & JEFI_FLAG_DERIV_SLOPE) ? kStencilSlope : 0) | (hold ? kStencilHold : 0) |
+              ((r.flags & JEFI_FLAG_TIME_CUBIC) ? kStencilCubic : 0);
   p.a_f = ts.a_f;
   p.inv_cdt = ts.inv_cdt;
   p.inv_dt = 1.0 / dt;
@@ -552,7 +555,7 @@ void drop_graphs(BatchWorkspace& w) {
 int slots_per_cu(int wz) { return wz == 2 ? 2 : 4; }
 constexpr int kItemsPerSlot = 12;
 
-jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, hipGraphExec_t* out) {
+jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, int cub, hipGraphExec_t* out) {
   hipGraph_t g;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
@@ -576,7 +579,7 @@ jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, hipGraph
     e = hipGraphAddKernelNode(&n1, g, &n0, 1, &kp);
   }
   if (e == hipSuccess) {
-    kp.func = batch_pair_kernel(is_f64, wz, idx);
+    kp.func = batch_pair_kernel(is_f64, wz, idx, cub);
     kp.gridDim = dim3(cus * slots_per_cu(wz));
     kp.blockDim = dim3(batch_pair_threads(wz));
     e = hipGraphAddKernelNode(&n2, g, &n1, 1, &kp);
@@ -991,11 +994,13 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
     drop_graphs(w);
     w.bd = bd;
   }
-  const int gkey = is_f64 * 8 + idx * 4 + wz;
+  // one stencil for the whole batch (the options are shared)
+  const int cub = nb > 0 && (params[0].stencil & kStencilCubic) ? 1 : 0;
+  const int gkey = cub * 16 + is_f64 * 8 + idx * 4 + wz;
   auto it = w.graphs.find(gkey);
   if (it == w.graphs.end()) {
     hipGraphExec_t ge;
-    jefi_status st = build_graph(w, is_f64, wz, idx, &ge);
+    jefi_status st = build_graph(w, is_f64, wz, idx, cub, &ge);
     if (st != JEFI_OK) return st;
     it = w.graphs.emplace(gkey, ge).first;
   }

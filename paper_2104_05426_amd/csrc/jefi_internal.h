@@ -25,9 +25,11 @@ struct GridD {
 
 // Everything a pair-kernel launch needs; passed by value.
 // Time-stencil readings (pair kernels): derivative as the slope of the
-// linear interpolant; history before the oldest slice held at its values.
+// linear interpolant; history before the oldest slice held at its values;
+// cubic time interpolation through slices k-2 .. k+1.
 constexpr int kStencilSlope = 1;
 constexpr int kStencilHold = 2;
+constexpr int kStencilCubic = 4;
 
 struct PairParams {
   GridD src, obs;
@@ -120,7 +122,7 @@ void* batch_reset_kernel();
 void* batch_threshold_kernel();
 // idx: index mode of the FP32 kernel (1 = threshold table for every pair,
 // needs use_thr in every instance; 0 = guard band).
-void* batch_pair_kernel(int is_f64, int wz, int idx);
+void* batch_pair_kernel(int is_f64, int wz, int idx, int cubic);
 void* batch_epilogue_kernel();
 int batch_pair_threads(int wz);
 hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);

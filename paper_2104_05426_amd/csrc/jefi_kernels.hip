@@ -276,6 +276,112 @@ __device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const D4
   l2[7 * PU + idx] = make_double2(Tn[2], Tn[3]);
 }
 
+// Entry of slot k for cubic time interpolation: the coefficients c0 .. c3 in
+// f of the cubic through raw slices k-2, k-1, k, k+1 (nodes -2 .. 1), taken
+// from differences to h_k so that equal slices give exactly zero higher
+// coefficients; value c0 + c1 f + c2 f^2 + c3 f^3, derivative in f
+// c1 + 2 c2 f + 3 c3 f^2 (scaled to time by the pair loop).
+__device__ __forceinline__ void cubic_coef(float h2, float h1, float h0, float hp, float c[4]) {
+  const float a = h2 - h0, b = h1 - h0, q = hp - h0;
+  c[0] = h0;
+  c[1] = __builtin_fmaf(a, 1.f / 6.f, __builtin_fmaf(q, 1.f / 3.f, -b));
+  c[2] = (b + q) * 0.5f;
+  c[3] = __builtin_fmaf(q - a, 1.f / 6.f, b * 0.5f);
+}
+
+__device__ __forceinline__ void cubic_coef(double h2, double h1, double h0, double hp, double c[4]) {
+  const double a = h2 - h0, b = h1 - h0, q = hp - h0;
+  c[0] = h0;
+  c[1] = __builtin_fma(a, 1.0 / 6.0, __builtin_fma(q, 1.0 / 3.0, -b));
+  c[2] = (b + q) * 0.5;
+  c[3] = __builtin_fma(q - a, 1.0 / 6.0, b * 0.5);
+}
+
+__device__ __forceinline__ void put_cubic(float4* lds, int PU, int idx, const float4& h2, const float4& h1,
+                                          const float4& h0, const float4& hp) {
+  float cx[4], cy[4], cz[4], cw[4];
+  cubic_coef(h2.x, h1.x, h0.x, hp.x, cx);
+  cubic_coef(h2.y, h1.y, h0.y, hp.y, cy);
+  cubic_coef(h2.z, h1.z, h0.z, hp.z, cz);
+  cubic_coef(h2.w, h1.w, h0.w, hp.w, cw);
+  for (int i = 0; i < 4; ++i) lds[i * PU + idx] = make_float4(cx[i], cy[i], cz[i], cw[i]);
+}
+
+__device__ __forceinline__ void put_cubic(float4* lds, int PU, int idx, const D4& h2, const D4& h1, const D4& h0,
+                                          const D4& hp) {
+  double cx[4], cy[4], cz[4], cw[4];
+  cubic_coef(h2.x, h1.x, h0.x, hp.x, cx);
+  cubic_coef(h2.y, h1.y, h0.y, hp.y, cy);
+  cubic_coef(h2.z, h1.z, h0.z, hp.z, cz);
+  cubic_coef(h2.w, h1.w, h0.w, hp.w, cw);
+  double2* l2 = (double2*)lds;
+  for (int i = 0; i < 4; ++i) {
+    l2[2 * i * PU + idx] = make_double2(cx[i], cy[i]);
+    l2[(2 * i + 1) * PU + idx] = make_double2(cz[i], cw[i]);
+  }
+}
+
+// Source values (rho, Jx, Jy, Jz) and their time derivatives at fraction f
+// of LDS entry e.  Linear planes (h, S, D, T): value h + f S, derivative
+// D + f T (the derivative planes carry the time unit).  Cubic planes
+// (c0 .. c3): value and derivative in one Horner pass, the derivative in f
+// times dsc (1/dt in the caller's time unit).
+template <bool CUB>
+__device__ __forceinline__ void entry_at(const float4* lds, int PU, int e, float f, float dsc, float v[4],
+                                         float w[4]) {
+  const float4 a4 = lds[e], b4 = lds[PU + e], c4 = lds[2 * PU + e], d4 = lds[3 * PU + e];
+  const float A[4] = {a4.x, a4.y, a4.z, a4.w}, Bq[4] = {b4.x, b4.y, b4.z, b4.w};
+  const float Cq[4] = {c4.x, c4.y, c4.z, c4.w}, Dq[4] = {d4.x, d4.y, d4.z, d4.w};
+  if constexpr (!CUB) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = __builtin_fmaf(f, Bq[q], A[q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = __builtin_fmaf(f, Dq[q], Cq[q]);
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    {
+      const float p1 = __builtin_fmaf(Dq[q], f, Cq[q]);
+      const float d1 = __builtin_fmaf(Dq[q], f, p1);
+      const float p2 = __builtin_fmaf(p1, f, Bq[q]);
+      const float d2 = __builtin_fmaf(d1, f, p2);
+      v[q] = __builtin_fmaf(p2, f, A[q]);
+      w[q] = d2 * dsc;
+    }
+  }
+}
+
+template <bool CUB>
+__device__ __forceinline__ void entry_at(const float4* lds, int PU, int e, double f, double dsc, double v[4],
+                                         double w[4]) {
+  const double2* l2 = (const double2*)lds;
+  double P[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 lo = l2[2 * i * PU + e], hi = l2[(2 * i + 1) * PU + e];
+    P[i][0] = lo.x; P[i][1] = lo.y; P[i][2] = hi.x; P[i][3] = hi.y;
+  }
+  if constexpr (!CUB) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = __builtin_fma(f, P[1][q], P[0][q]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = __builtin_fma(f, P[3][q], P[2][q]);
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    {
+      const double p1 = __builtin_fma(P[3][q], f, P[2][q]);
+      const double d1 = __builtin_fma(P[3][q], f, p1);
+      const double p2 = __builtin_fma(p1, f, P[1][q]);
+      const double d2 = __builtin_fma(d1, f, p2);
+      v[q] = __builtin_fma(p2, f, P[0][q]);
+      w[q] = d2 * dsc;
+    }
+  }
+}
+
 // Geometry of one observation tile: first/last point indices, the FP64
 // reference point (first point) and the far corner of its box.
 struct TileGeom {
@@ -454,7 +560,11 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
         load_raw(ring, p, k - 1, ti.w, c, hm);
         load_raw(ring, p, k, ti.w, c, h0);
         load_raw(ring, p, k + 1, ti.w, c, h1);
-        if (p.stencil & kStencilSlope)
+        if (p.stencil & kStencilCubic) {
+          typename RawOf<T>::type h2;
+          load_raw(ring, p, k - 2, ti.w, c, h2);
+          put_cubic(lds, PU, e, h2, hm, h0, h1);
+        } else if (p.stencil & kStencilSlope)
           put_entry<true>(lds, PU, e, hm, h0, h1, inv_dt);
         else
           put_entry<false>(lds, PU, e, hm, h0, h1, inv_dt);
@@ -524,20 +634,15 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
               continue;
             }
             const int e = base + c * kWmax + kc;
-            const float4 hv = lds[e];
-            const float4 Sv = lds[PU + e];
-            const float4 Dv = lds[2 * PU + e];
-            const float4 Tv = lds[3 * PU + e];
             const float ri2 = ri * ri;
             const float ri3 = ri2 * ri;
-            const float rho = __builtin_fmaf(f, Sv.x, hv.x);
-            const float jx = __builtin_fmaf(f, Sv.y, hv.y);
-            const float jy = __builtin_fmaf(f, Sv.z, hv.z);
-            const float jz = __builtin_fmaf(f, Sv.w, hv.w);
-            const float rhod = __builtin_fmaf(f, Tv.x, Dv.x);
-            const float jdx = __builtin_fmaf(f, Tv.y, Dv.y);
-            const float jdy = __builtin_fmaf(f, Tv.z, Dv.z);
-            const float jdz = __builtin_fmaf(f, Tv.w, Dv.w);
+            float v[4], w[4];
+            if (p.stencil & kStencilCubic)
+              entry_at<true>(lds, PU, e, f, inv_dt, v, w);
+            else
+              entry_at<false>(lds, PU, e, f, inv_dt, v, w);
+            const float rho = v[0], jx = v[1], jy = v[2], jz = v[3];
+            const float rhod = w[0], jdx = w[1], jdy = w[2], jdz = w[3];
             const float a = __builtin_fmaf(rho, ri3, rhod * ri2);
             bE[0] = __builtin_fmaf(dx, a, bE[0]);
             bE[1] = __builtin_fmaf(dy, a, bE[1]);
@@ -583,20 +688,14 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
             ri = __builtin_fma(ri, er, ri);
             const double ri2 = ri * ri;
             const double ri3 = ri2 * ri;
-            const double2* l2 = (const double2*)lds;
             const int e = base + c * kWmax + kc;
-            const double2 h01 = l2[e], h23 = l2[PU + e];
-            const double2 S01 = l2[2 * PU + e], S23 = l2[3 * PU + e];
-            const double2 D01 = l2[4 * PU + e], D23 = l2[5 * PU + e];
-            const double2 T01 = l2[6 * PU + e], T23 = l2[7 * PU + e];
-            const double rho = __builtin_fma(f, S01.x, h01.x);
-            const double jx = __builtin_fma(f, S01.y, h01.y);
-            const double jy = __builtin_fma(f, S23.x, h23.x);
-            const double jz = __builtin_fma(f, S23.y, h23.y);
-            const double rhod = __builtin_fma(f, T01.x, D01.x);
-            const double jdx = __builtin_fma(f, T01.y, D01.y);
-            const double jdy = __builtin_fma(f, T23.x, D23.x);
-            const double jdz = __builtin_fma(f, T23.y, D23.y);
+            double v[4], w[4];
+            if (p.stencil & kStencilCubic)
+              entry_at<true>(lds, PU, e, f, (double)inv_dt, v, w);
+            else
+              entry_at<false>(lds, PU, e, f, (double)inv_dt, v, w);
+            const double rho = v[0], jx = v[1], jy = v[2], jz = v[3];
+            const double rhod = w[0], jdx = w[1], jdy = w[2], jdz = w[3];
             const double a = __builtin_fma(rho, ri3, rhod * ri2);
             dE[0] = __builtin_fma(dx, a, dE[0]);
             dE[1] = __builtin_fma(dy, a, dE[1]);
@@ -676,20 +775,13 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
 // then branch-free LDS reads and field arithmetic.
 
 // Field contribution of one pair from its LDS entry (FP32).
+template <bool CUB>
 __device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, float f, float ri, float dx,
-                                            float dy, float dz, float bE[3], float bB[3]) {
-  const float4 hv = lds[e];
-  const float4 Sv = lds[PU + e];
-  const float4 Dv = lds[2 * PU + e];
-  const float4 Tv = lds[3 * PU + e];
-  const float rho = __builtin_fmaf(f, Sv.x, hv.x);
-  const float jx = __builtin_fmaf(f, Sv.y, hv.y);
-  const float jy = __builtin_fmaf(f, Sv.z, hv.z);
-  const float jz = __builtin_fmaf(f, Sv.w, hv.w);
-  const float rhod = __builtin_fmaf(f, Tv.x, Dv.x);
-  const float jdx = __builtin_fmaf(f, Tv.y, Dv.y);
-  const float jdy = __builtin_fmaf(f, Tv.z, Dv.z);
-  const float jdz = __builtin_fmaf(f, Tv.w, Dv.w);
+                                            float dy, float dz, float bE[3], float bB[3], float dsc) {
+  float v[4], w[4];
+  entry_at<CUB>(lds, PU, e, f, dsc, v, w);
+  const float rho = v[0], jx = v[1], jy = v[2], jz = v[3];
+  const float rhod = w[0], jdx = w[1], jdy = w[2], jdz = w[3];
   // E += d/R^2 (rho/R + rho_dot) - J_dot/R ;  B += (J/R + J_dot) x d/R^2
   const float ri2 = ri * ri;
   const float ux = dx * ri2, uy = dy * ri2, uz = dz * ri2;
@@ -712,26 +804,18 @@ __device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, fl
 }
 
 // Field contribution of one pair from its LDS entry (FP64).
+template <bool CUB>
 __device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, double f, double R, double dx,
-                                            double dy, double dz, double dE[3], double dB[3]) {
+                                            double dy, double dz, double dE[3], double dB[3], double dsc) {
   double ri = __builtin_amdgcn_rcp(R);
   double er = __builtin_fma(-R, ri, 1.0);
   ri = __builtin_fma(ri, er, ri);
   er = __builtin_fma(-R, ri, 1.0);
   ri = __builtin_fma(ri, er, ri);
-  const double2* l2 = (const double2*)lds;
-  const double2 h01 = l2[e], h23 = l2[PU + e];
-  const double2 S01 = l2[2 * PU + e], S23 = l2[3 * PU + e];
-  const double2 D01 = l2[4 * PU + e], D23 = l2[5 * PU + e];
-  const double2 T01 = l2[6 * PU + e], T23 = l2[7 * PU + e];
-  const double rho = __builtin_fma(f, S01.x, h01.x);
-  const double jx = __builtin_fma(f, S01.y, h01.y);
-  const double jy = __builtin_fma(f, S23.x, h23.x);
-  const double jz = __builtin_fma(f, S23.y, h23.y);
-  const double rhod = __builtin_fma(f, T01.x, D01.x);
-  const double jdx = __builtin_fma(f, T01.y, D01.y);
-  const double jdy = __builtin_fma(f, T23.x, D23.x);
-  const double jdz = __builtin_fma(f, T23.y, D23.y);
+  double v[4], w[4];
+  entry_at<CUB>(lds, PU, e, f, dsc, v, w);
+  const double rho = v[0], jx = v[1], jy = v[2], jz = v[3];
+  const double rhod = w[0], jdx = w[1], jdy = w[2], jdz = w[3];
   const double ri2 = ri * ri;
   const double ux = dx * ri2, uy = dy * ri2, uz = dz * ri2;
   const double ap = __builtin_fma(rho, ri, rhod);
@@ -786,7 +870,7 @@ struct FastShape {
 // 1 = threshold-table decision for every pair of a full brick.  PP is
 // PairParams as a kernel argument, or in the constant address space for
 // the persistent kernel (uniform, read-only: scalar loads).
-template <typename T, int WZ, bool FP, int IDX, int W, class PP>
+template <typename T, int WZ, bool FP, int IDX, int W, bool CUB, class PP>
 __device__ __forceinline__ void pair_body(const PP& p, int bid,
                                           float4 (&lds)[FastShape<T, WZ, W>::NPL * FastShape<T, WZ, W>::PU],
                                           int4 (&tab_i)[kBrickRing], float4 (&tab_f)[kBrickRing],
@@ -798,7 +882,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   constexpr int PU = FastShape<T, WZ, W>::PU;
   constexpr int kCellStride = FastShape<T, WZ, W>::CS;
   constexpr int EPT = G * kBrickCells * W / kThreads;  // staged entries per thread
-  constexpr int NRAW = EPT + 2;
+  constexpr int NRAW = EPT + (CUB ? 3 : 2);  // raw slices k0-1 (k0-2 for the cubic) .. k0+EPT
   constexpr int NQ = W / EPT;
   static_assert(EPT >= 1 && EPT * kThreads == G * kBrickCells * W, "staging map");
 
@@ -891,11 +975,12 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       const __amdgpu_buffer_rsrc_t rs =
           __builtin_amdgcn_make_buffer_rsrc((void*)p.ring, (short)0, (int)p.ring_bytes_rs, kRawBufferFlags);
       const unsigned sb = (unsigned)p.slot_elems * (unsigned)sizeof(T);
-      const int j0 = (ti.z & 1) ? p.nt : k0 - 1;  // dead bricks: every load out of range
-      int sl = p.slot_base + j0;  // j0 >= -3
+      const int j0 = (ti.z & 1) ? p.nt : k0 - (CUB ? 2 : 1);  // dead bricks: every load out of range
+      int sl = p.slot_base + j0;  // j0 >= -3 (-4 for the cubic)
       sl += sl < 0 ? p.capacity : 0;
       sl += sl < 0 ? p.capacity : 0;
       sl += sl < 0 ? p.capacity : 0;
+      if constexpr (CUB) sl += sl < 0 ? p.capacity : 0;
       sl -= sl >= p.capacity ? p.capacity : 0;
       const unsigned cell_off = ((unsigned)ti.w * kBrickCells + (unsigned)sc) * (4u * (unsigned)sizeof(T));
       unsigned off = (unsigned)sl * sb + cell_off;
@@ -926,12 +1011,19 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       if (ti.z & 1)
         zero_raw(raw[r]);
       else
-        load_raw(ring, p, k0 - 1 + r, ti.w, sc, raw[r]);
+        load_raw(ring, p, k0 - (CUB ? 2 : 1) + r, ti.w, sc, raw[r]);
     }
   };
   auto write_round = [&](int pos, int n) {
     const int4 ti = slot_entry(pos, n, sj);
     if (ti.z & 1) return;
+    if constexpr (CUB) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e)
+        put_cubic(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1], raw[e + 2],
+                  raw[e + 3]);
+      return;
+    }
     if (p.stencil & kStencilSlope) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e)
@@ -1103,13 +1195,13 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           if (!(p.stencil & kStencilHold) && !__any(mmax >= -1 - p.a_i)) continue;
 #pragma unroll
           for (int c = 0; c < 8; ++c)
-            pair_fields(lds, PU, cellbase + c * kCellStride + max(m[c], mlo), fr[c], ri[c], (c & 1) ? d1x : d0x,
-                        ((c >> 1) & 1) ? d1y : d0y, (c >> 2) ? d1z : d0z, bE, bB);
+            pair_fields<CUB>(lds, PU, cellbase + c * kCellStride + max(m[c], mlo), fr[c], ri[c],
+                             (c & 1) ? d1x : d0x, ((c >> 1) & 1) ? d1y : d0y, (c >> 2) ? d1z : d0z, bE, bB, inv_dt);
         } else {
 #pragma unroll
           for (int c = 0; c < 8; ++c)
-            pair_fields(lds, PU, cellbase + c * kCellStride + m[c], fr[c], ri[c], (c & 1) ? d1x : d0x,
-                        ((c >> 1) & 1) ? d1y : d0y, (c >> 2) ? d1z : d0z, bE, bB);
+            pair_fields<CUB>(lds, PU, cellbase + c * kCellStride + m[c], fr[c], ri[c], (c & 1) ? d1x : d0x,
+                             ((c >> 1) & 1) ? d1y : d0y, (c >> 2) ? d1z : d0z, bE, bB, inv_dt);
         }
       }
 #pragma unroll 1
@@ -1148,7 +1240,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
             continue;
           }
           const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
-          pair_fields(lds, PU, e, f, ri, dx, dy, dz, bE, bB);
+          pair_fields<CUB>(lds, PU, e, f, ri, dx, dy, dz, bE, bB, inv_dt);
         }
       }
       if (!FP && (++n_blk & 1) == 0) {
@@ -1201,7 +1293,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
             continue;
           }
           const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
-          pair_fields(lds, PU, e, u - fl, R, dx[cx], dy[cy], dz[cz], dE, dB);
+          pair_fields<CUB>(lds, PU, e, u - fl, R, dx[cx], dy[cy], dz[cz], dE, dB, inv_dt);
         }
       }
     }
@@ -1257,7 +1349,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   }
 }
 
-template <typename T, int WZ, bool FP, int IDX, int W>
+template <typename T, int WZ, bool FP, int IDX, int W, bool CUB>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
   using S = FastShape<T, WZ, W>;
   __shared__ float4 lds[S::NPL * S::PU];
@@ -1266,13 +1358,14 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ double tab_c[kBrickRing][6];
   __shared__ double thr[S::THR];
   __shared__ int qs[2];
-  pair_body<T, WZ, FP, IDX, W>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab_i, tab_f, tab_c, thr, qs);
+  pair_body<T, WZ, FP, IDX, W, CUB>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab_i, tab_f,
+                                    tab_c, thr, qs);
 }
 
 // Persistent batched launch: workgroups pull (instance, workgroup id) items
 // from a queue ordered heaviest first until it is empty.  IDX as for
 // pair_body, one value for the whole batch.
-template <typename T, int WZ, int IDX>
+template <typename T, int WZ, int IDX, bool CUB>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_persistent(BatchDevice bd) {
   using S = FastShape<T, WZ, 32>;
   __shared__ float4 lds[S::NPL * S::PU];
@@ -1294,7 +1387,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
     using CP = const __attribute__((address_space(4))) PairParams;
     CP& p = *(CP*)(bd.params + inst);
-    pair_body<T, WZ, false, IDX, 32>(p, bid, lds, tab_i, tab_f, tab_c, thr, qs);
+    pair_body<T, WZ, false, IDX, 32, CUB>(p, bid, lds, tab_i, tab_f, tab_c, thr, qs);
   }
 }
 
@@ -1540,10 +1633,19 @@ hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, i
 hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk, int wsel,
                         hipStream_t s) {
   dim3 grid(p.n_wg), block(kThreads);
+  // the fingerprint pass takes slice decisions only: no cubic variant
+  const bool cub = !fingerprint && (p.stencil & kStencilCubic) != 0;
 #define JEFI_LAUNCH(T, G, FPM, MUL) \
   hipLaunchKernelGGL((pair_kernel<T, G, FPM, MUL>), grid, block, 0, s, p)
-#define JEFI_FAST(T, WZ, FPM, IDX, W) \
-  hipLaunchKernelGGL((pair_kernel_fast<T, WZ, FPM, IDX, W>), grid, dim3(256 * WZ), 0, s, p)
+#define JEFI_FAST(T, WZ, FPM, IDX, W)                                                                    \
+  do {                                                                                                  \
+    if (FPM)                                                                                            \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, true, IDX, W, false>), grid, dim3(256 * WZ), 0, s, p); \
+    else if (cub)                                                                                       \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, true>), grid, dim3(256 * WZ), 0, s, p); \
+    else                                                                                                \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, false>), grid, dim3(256 * WZ), 0, s, p); \
+  } while (0)
 #define JEFI_FAST_F32(WZ, FPM, W)        \
   do {                                  \
     if (p.exact_idx)                    \
@@ -1605,12 +1707,19 @@ hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt,
 void* batch_reset_kernel() { return (void*)batch_reset; }
 void* batch_threshold_kernel() { return (void*)batch_threshold; }
 void* batch_epilogue_kernel() { return (void*)batch_epilogue; }
-void* batch_pair_kernel(int is_f64, int wz, int idx) {
+void* batch_pair_kernel(int is_f64, int wz, int idx, int cubic) {
+  if (cubic) {
+    if (is_f64)
+      return wz == 2 ? (void*)pair_kernel_persistent<double, 2, 0, true> : (void*)pair_kernel_persistent<double, 1, 0, true>;
+    if (idx)
+      return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 1, true> : (void*)pair_kernel_persistent<float, 1, 1, true>;
+    return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 0, true> : (void*)pair_kernel_persistent<float, 1, 0, true>;
+  }
   if (is_f64)
-    return wz == 2 ? (void*)pair_kernel_persistent<double, 2, 0> : (void*)pair_kernel_persistent<double, 1, 0>;
+    return wz == 2 ? (void*)pair_kernel_persistent<double, 2, 0, false> : (void*)pair_kernel_persistent<double, 1, 0, false>;
   if (idx)
-    return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 1> : (void*)pair_kernel_persistent<float, 1, 1>;
-  return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 0> : (void*)pair_kernel_persistent<float, 1, 0>;
+    return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 1, false> : (void*)pair_kernel_persistent<float, 1, 1, false>;
+  return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 0, false> : (void*)pair_kernel_persistent<float, 1, 0, false>;
 }
 int batch_pair_threads(int wz) { return 256 * wz; }
 

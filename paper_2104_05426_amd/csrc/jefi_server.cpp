@@ -468,9 +468,12 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
   if (!cfg || !out) return JEFI_EINVAL;
   if (!cfg->arena || cfg->arena_bytes < Arena::kGranule) return JEFI_EINVAL;
   if (cfg->precision != JEFI_PREC_F64 && cfg->precision != JEFI_PREC_F32_COMP) return JEFI_EINVAL;
-  const uint32_t known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_PAST_HOLD;
+  const uint32_t known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_PAST_HOLD |
+                         JEFI_FLAG_TIME_CUBIC;
   const uint32_t both = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE;
-  if ((cfg->flags & ~known) != 0 || (cfg->flags & both) == both) return JEFI_EINVAL;
+  const uint32_t slope_cubic = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
+  if ((cfg->flags & ~known) != 0 || (cfg->flags & both) == both || (cfg->flags & slope_cubic) == slope_cubic)
+    return JEFI_EINVAL;
   jefi_server* sv = new jefi_server();
   sv->cfg = *cfg;
   if (sv->cfg.max_inflight < 1) sv->cfg.max_inflight = 2;

@@ -273,6 +273,8 @@ void option_flags() {
   CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
   cfg.flags = 64;
   CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
+  cfg.flags = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
+  CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
   std::vector<char> ar;
   const uint32_t flags = JEFI_FLAG_PAST_HOLD | JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_INDEX_TABLE;
   jefi_server* sv = make_server(8 << 20, 2, 64, ar, flags);
@@ -284,6 +286,17 @@ void option_flags() {
   check_result(sv, p);
   CHECK(g_last_batch_flags.load() == flags);
   CHECK(jefi_server_destroy(sv) == JEFI_OK);
+  // the cubic reading reaches the evaluations the same way
+  const uint32_t cflags = JEFI_FLAG_PAST_HOLD | JEFI_FLAG_TIME_CUBIC;
+  std::vector<char> ar2;
+  jefi_server* sv2 = make_server(8 << 20, 2, 64, ar2, cflags);
+  std::vector<Session> ss2 = {{43, 3, 0}};
+  open_sessions(sv2, ss2, 2);
+  Pending p2;
+  submit(sv2, ss2[0], p2, 2);
+  check_result(sv2, p2);
+  CHECK(g_last_batch_flags.load() == cflags);
+  CHECK(jefi_server_destroy(sv2) == JEFI_OK);
 }
 
 }  // namespace

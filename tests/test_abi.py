@@ -56,7 +56,7 @@ def _grid(n=(4, 4, 4), h=0.1):
 @pytest.mark.parametrize("case", [
     "null-src", "bad-spacing", "nt-zero", "nt-over-capacity", "nt-over-pushed", "t-after-newest",
     "dtype-mismatch", "bad-c", "negative-screen", "null-out", "bad-dt", "bad-flags", "both-flags",
-    "bad-tile",
+    "slope-and-cubic", "bad-tile",
 ])
 def test_eval_validation(case):
     """Each bad input returns EINVAL with a message, before any device call."""
@@ -91,7 +91,9 @@ def test_eval_validation(case):
     elif case == "bad-dt":
         dt = 0.0
     elif case == "bad-flags":
-        opt.flags = 16
+        opt.flags = 32
+    elif case == "slope-and-cubic":
+        opt.flags = J.JEFI_FLAG_DERIV_SLOPE | J.JEFI_FLAG_TIME_CUBIC
     elif case == "both-flags":
         opt.flags = J.JEFI_FLAG_INDEX_GUARD | J.JEFI_FLAG_INDEX_TABLE | J.JEFI_FLAG_PAST_HOLD
     elif case == "bad-tile":

@@ -131,7 +131,8 @@ def _check_solo(J, reqs, full, n_oracle=4, prec="f32", flags=0):
         if i < n_oracle:
             p = Problem("srv", s["src"], r["obs"], window, s["dt"], t, 0.0, r["newest"], 1.0,
                         workloads.default_screen(s["src"]))
-            Er, Br = oracle.eval_problem(p, stencil=(flags >> 2) & 3)
+            # library stencil flags 4, 8, 16 -> oracle stencil bits 1, 2, 4
+            Er, Br = oracle.eval_problem(p, stencil=(flags >> 2) & 7)
             e, _ = rel_l2(r["E"].astype(np.float64), Er)
             b, _ = rel_l2(r["B"].astype(np.float64), Br)
             assert max(e + b) <= ORACLE_TOL[prec], (i, e, b)
@@ -170,14 +171,15 @@ def test_server_fp64_results_equal_solo():
     _check_solo(J, reqs, full, n_oracle=3, prec="f64")
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_server_with_stencil_flags(prec):
-    """A server whose evaluations use both alternative stencil readings
-    (slope derivative, held past) and the table index mode: every result
-    equals the same evaluation alone with those flags, and the oracle with
-    those readings."""
+@pytest.mark.parametrize("prec,reading", [("f32", "slope"), ("f64", "slope"), ("f32", "cubic"), ("f64", "cubic")])
+def test_server_with_stencil_flags(prec, reading):
+    """A server whose evaluations use alternative stencil readings (slope
+    derivative or cubic interpolation, with the held past) and the table
+    index mode: every result equals the same evaluation alone with those
+    flags, and the oracle with those readings."""
     J = _gpu()
-    flags = J.JEFI_FLAG_DERIV_SLOPE | J.JEFI_FLAG_PAST_HOLD | (J.JEFI_FLAG_INDEX_TABLE if prec == "f32" else 0)
+    flags = (J.JEFI_FLAG_DERIV_SLOPE if reading == "slope" else J.JEFI_FLAG_TIME_CUBIC) | J.JEFI_FLAG_PAST_HOLD | \
+        (J.JEFI_FLAG_INDEX_TABLE if prec == "f32" else 0)
     reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=4, n_req=20, seed=12, prec=prec, flags=flags)
     assert stats["completed"] == 20 and stats["failed"] == 0
     _check_solo(J, reqs, full, n_oracle=3, prec=prec, flags=flags)

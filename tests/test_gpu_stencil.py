@@ -1,7 +1,8 @@
 """The alternative time-stencil readings on the GPU against the oracle with
 the same readings: JEFI_FLAG_DERIV_SLOPE (derivative = slope of the linear
-interpolant) and JEFI_FLAG_PAST_HOLD (history before the oldest slice held
-at its values), alone and together.  Tiny and ragged problems in both
+interpolant), JEFI_FLAG_PAST_HOLD (history before the oldest slice held at
+its values) and JEFI_FLAG_TIME_CUBIC (cubic through slices k-2 .. k+1),
+alone and together.  Tiny and ragged problems in both
 precisions and tile shapes, evaluation times before the window, the 64- and
 128-slot staging shapes and the chunked kernel, a ring above 2 GiB (64-bit
 staging addresses), the batched persistent path, and fingerprints that the
@@ -22,7 +23,8 @@ TOL = {"f64": 1e-12, "f32": 1e-5}
 SOLO = {"f64": 1e-13, "f32": 2e-6}
 # library flag -> oracle stencil bits
 VARIANTS = {"slope": (4, oracle.STENCIL_SLOPE), "hold": (8, oracle.STENCIL_HOLD),
-            "both": (12, oracle.STENCIL_SLOPE | oracle.STENCIL_HOLD)}
+            "both": (12, oracle.STENCIL_SLOPE | oracle.STENCIL_HOLD),
+            "cubic": (16, oracle.STENCIL_CUBIC), "cubic+hold": (24, oracle.STENCIL_CUBIC | oracle.STENCIL_HOLD)}
 
 
 def _gpu():
@@ -60,7 +62,7 @@ def test_tiny_and_ragged(variant):
             assert np.array_equal(G.gpu_fingerprint(p, prec, flags=flag), fp_ref), (p.name, variant, prec)
 
 
-@pytest.mark.parametrize("variant", ["hold", "both"])
+@pytest.mark.parametrize("variant", ["hold", "both", "cubic+hold"])
 def test_times_before_the_window(variant):
     """Evaluation times before the oldest slice (every stencil in the past,
     a_i <= -2) and just after it (a_i = -1, 0): the held past gives the
@@ -81,13 +83,13 @@ def test_times_before_the_window(variant):
             assert np.all(Ez == 0.0) and np.all(Bz == 0.0)
 
 
-@pytest.mark.parametrize("ratio", [4, 8, 10])
-def test_staging_window_sizes(ratio):
-    """Both readings together on the 64- and 128-slot staging shapes and
-    the chunked kernel (spacing / (c dt) = 4, 8, 10), with a window shorter
-    than the longest separation (pairs in the held past)."""
+@pytest.mark.parametrize("ratio,variant", [(r, v) for r in (4, 8, 10) for v in ("both", "cubic+hold", "cubic")])
+def test_staging_window_sizes(ratio, variant):
+    """Readings on the 64- and 128-slot staging shapes and the chunked
+    kernel (spacing / (c dt) = 4, 8, 10), with a window shorter than the
+    longest separation (pairs in the past)."""
     G = _gpu()
-    flag, st = VARIANTS["both"]
+    flag, st = VARIANTS[variant]
     h = 0.1
     src = centred_grid((10, 9, 11), h)
     obs = Grid((9, 10, 8), tuple(src.origin[a] + (3, -2, 4)[a] * h for a in range(3)), (h, h, h))
@@ -100,18 +102,18 @@ def test_staging_window_sizes(ratio):
     Er, Br = oracle.eval_problem(p, stencil=st)
     for prec in ["f64", "f32"]:
         Eg, Bg = G.gpu_eval(p, prec, flags=flag)
-        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"window ratio {ratio} both {prec}")
+        _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"window ratio {ratio} {variant} {prec}")
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_ring_above_2gib(prec):
+@pytest.mark.parametrize("prec,variant", [("f32", "both"), ("f64", "both"), ("f32", "cubic"), ("f64", "cubic+hold")])
+def test_ring_above_2gib(prec, variant):
     """A ring of more than 2 GiB (64-bit staging addresses, no buffer
-    addressing) with both readings: identical to a ring holding only the
+    addressing) with the readings: identical to a ring holding only the
     used steps, and the oracle's fields on sampled points."""
     import torch
     import paper_2104_05426_amd as J
     _gpu()
-    flag, st = VARIANTS["both"]
+    flag, st = VARIANTS[variant]
     src = centred_grid((64, 64, 64), 0.025)
     obs = Grid((8, 8, 8), tuple(src.origin[a] + (28 + (8 if a == 0 else 0)) * 0.025 for a in range(3)),
                (0.025, 0.025, 0.025))
@@ -139,7 +141,7 @@ def test_ring_above_2gib(prec):
     sel = np.sort(np.random.default_rng(5).choice(obs.size, size=24, replace=False))
     p = Problem("big-ring", src, obs, hall[total - nt:], dt, t, 0.0, total - 1, 1.0, workloads.default_screen(src))
     Er, Br = oracle.eval_problem(p, sel=sel, stencil=st)
-    _assert_fields(outs[0][0][:, sel], outs[0][1][:, sel], Er, Br, TOL[prec], f"ring > 2 GiB both {prec}")
+    _assert_fields(outs[0][0][:, sel], outs[0][1][:, sel], Er, Br, TOL[prec], f"ring > 2 GiB {variant} {prec}")
 
 
 @pytest.mark.parametrize("variant", sorted(VARIANTS))
