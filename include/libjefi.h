@@ -338,7 +338,8 @@ jefi_status jefi_slice_index_dump(const jefi_grid* src, int32_t nt, double dt, i
  * (same tiling, staging windows, culling and index code), DEVICE int64
  * fp[n_obs][4]: number of pairs that are neither screened nor wholly before
  * the oldest slice, the sum of their k, the sum of k*(s+1) (wrapping, s =
- * linear source index), and the number of screened pairs met. */
+ * linear source index), and the number of screened pairs (all of them, also
+ * those wholly before the oldest slice). */
 jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* hist, double dt,
                                    int32_t nt, const jefi_grid* obs, double t,
                                    const jefi_options* opt, int64_t* fp, void* stream);

@@ -769,7 +769,8 @@ jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* his
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_zero(fp, (unsigned long long)c.no * 4 * sizeof(int64_t), s);
   if (e != hipSuccess) return hip_fail(e, "fingerprint zero-fill");
-  if (c.ns == 0 || c.plan.all_dead) return JEFI_OK;
+  // every pair wholly in the past still runs: screened pairs are counted
+  if (c.ns == 0) return JEFI_OK;
   PairParams& p = c.plan.p;
   attach_history(p, hist, nt);
   p.fp = (unsigned long long*)fp;

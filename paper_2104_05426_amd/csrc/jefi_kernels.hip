@@ -541,6 +541,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
         if (!(ti.z & 1)) wmax_round = max(wmax_round, ti.y - ti.x + 1);
       }
       n_chunks = (wmax_round + kWmax - 1) / kWmax;
+      if (FP) n_chunks = max(n_chunks, 1);  // screened pairs of dead bricks are still counted
     }
 
     for (int ch = 0; ch < n_chunks; ++ch) {
@@ -575,7 +576,9 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
       float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
       for (int j = 0; j < G; ++j) {
         const int4 ti = tab_i[j];
-        if (ti.z & 1) continue;
+        const bool dead = (ti.z & 1) != 0;
+        // the fingerprint pass counts the screened pairs of dead near bricks too
+        if (dead && !(FP && (ti.z & 2))) continue;
         const float4 tf = tab_f[j];
         const bool near = (ti.z & 2) != 0;
         const int vmask = ti.z >> 8;
@@ -609,7 +612,7 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
               if (FP && cs == 0) n_scr += 1;
             }
           }
-          if (!act) continue;
+          if (!act || dead) continue;
           if constexpr (sizeof(T) == 4) {
             const float dx = cx ? d0x - hsx : d0x;
             const float dy = cy ? d0y - hsy : d0y;
@@ -943,7 +946,9 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       float4 tf;
       double cc[6];
       brick_info(p, tg, cursor + t, b_end, ti, tf, cc);  // past b_end: a dead entry
-      const bool live = !(ti.z & 1);
+      // the fingerprint pass also takes dead bricks that may hold screened
+      // pairs: it counts every screened pair
+      const bool live = !(ti.z & 1) || (FP && (ti.z & 2));
       const unsigned long long m = __ballot(live);
       const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
       const int got = (int)__popcll(m);
@@ -1088,7 +1093,10 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       for (int j = 0; j < cnt; ++j) {
         const int q = (pos + j) & (kBrickRing - 1);
         const int tz = __builtin_amdgcn_readfirstlane(tab_i[q].z);
-        if (tz & 1) continue;
+        if (tz & 1) {
+          if (FP && (tz & 2)) slow |= 1u << j;  // fingerprint: count its screened pairs
+          continue;
+        }
         if ((tz & 0xff02) != 0xff00) {
           slow |= 1u << j;
           continue;
@@ -1255,7 +1263,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       for (int j = 0; j < cnt; ++j) {
         const int q = (pos + j) & (kBrickRing - 1);
         const int4 ti = tab_i[q];
-        if (ti.z & 1) continue;
+        if ((ti.z & 1) && !(FP && (ti.z & 2))) continue;  // fingerprint: dead near bricks still count screening
         const int lo = ti.x;
         const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;

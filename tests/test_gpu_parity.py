@@ -165,6 +165,34 @@ def _ragged_problem(seed, smooth=True):
     return Problem(f"ragged{seed}", src, obs, hist, dt, t, 0.0, newest, c, screen)
 
 
+@pytest.mark.parametrize("when,ratio", [("all-past", 2), ("front", 2), ("front", 10)])
+def test_fingerprint_counts_screened_pairs_in_the_past(when, ratio):
+    """Every screened pair is counted, also where a brick lies wholly before
+    the oldest slice: a time before the window (every brick dead) and a time
+    just after its start with a screening cube of several cells, so that
+    near bricks are dead too (spacing / (c dt) = 10 takes the chunked
+    kernel).  Fingerprints against the oracle, both precisions and tiles."""
+    G = _gpu()
+    h = 0.05
+    src = Grid((12, 10, 9), (-0.3, -0.2, -0.25), (h, h, h))
+    obs = Grid((9, 11, 6), tuple(src.origin[a] + (3, -2, 1)[a] * h for a in range(3)), (h, h, h))
+    dt, nt, s_old = h / ratio, 4 * ratio, 5
+    newest = s_old + nt - 1
+    hist = blob_history(src, [Blob(1.0, 0.1, (0.0, 0.0, 0.0), (0.2, 0.0, 0.1))], list(range(s_old, newest + 1)), dt)
+    # evaluation time in steps after the oldest slice: before it, or where only
+    # pairs closer than about 3 spacings are live (inside the screening cube's reach)
+    x = -3.2 if when == "all-past" else 3.0 * ratio - 0.9
+    p = Problem(f"screened-{when}-{ratio}", src, obs, hist, dt, (s_old + x) * dt, 0.0, newest, 1.0,
+                (2.5 * h, 2.5 * h, 2.5 * h))
+    fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)
+    assert fp_ref[:, 3].sum() > 0
+    assert (fp_ref[:, 0].sum() > 0) == (when == "front")
+    for prec in ["f64", "f32"]:
+        for tile in [1, 2]:
+            fp = G.gpu_fingerprint(p, prec, tile=tile)
+            assert np.array_equal(fp, fp_ref), (p.name, prec, tile, fp.sum(axis=0), fp_ref.sum(axis=0))
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_ragged_random_problems(seed):
     """Ragged grid sizes (partial tiles and bricks), unequal spacings, c != 1,
