@@ -335,6 +335,18 @@ def run_serve_workload(args):
 
     wall_p, lat_p, bsz_p, outs_p, stats_p = serve(paced=True)
     log(f"paced: {len(reqs)/wall_p:.1f} req/s, p50 {np.percentile(lat_p, 50):.2f} ms p99 {np.percentile(lat_p, 99):.2f} ms")
+    # paced latency by request size (source cells x observation points, quartiles)
+    req_pairs = pairs
+    cls = np.digitize(req_pairs, np.quantile(req_pairs, [0.25, 0.5, 0.75]))
+    by_size = []
+    for q in range(4):
+        m = cls == q
+        if m.any():
+            by_size.append({"pairs_median": float(f"{np.median(req_pairs[m]):.3e}"), "requests": int(m.sum()),
+                            "p50": round(float(np.percentile(lat_p[m], 50)), 3),
+                            "p99": round(float(np.percentile(lat_p[m], 99)), 3)})
+    log("paced latency by size quartile: " + ", ".join(f"{d['pairs_median']:.1e} pairs p50 {d['p50']} p99 {d['p99']} ms"
+                                                      for d in by_size))
     wall_o, lat_o, bsz_o, outs_o, stats_o = serve(paced=False)
     log(f"back-to-back: {len(reqs)/wall_o:.1f} req/s")
 
@@ -403,7 +415,8 @@ def run_serve_workload(args):
                   "latency_ms": {"p50": round(float(np.percentile(lat_p, 50)), 3),
                                  "p99": round(float(np.percentile(lat_p, 99)), 3),
                                  "max": round(float(lat_p.max()), 3)},
-                  "mean_batch": round(float(bsz_p.mean()), 2), "batches": stats_p["batches"]},
+                  "mean_batch": round(float(bsz_p.mean()), 2), "batches": stats_p["batches"],
+                  "latency_ms_by_size_quartile": by_size},
         "back_to_back_latency_ms": {"p50": round(float(np.percentile(lat_o, 50)), 3),
                                     "p99": round(float(np.percentile(lat_o, 99)), 3)},
         "fp64_one_launch_per_request": {"req_per_s": round(len(reqs) / wall64, 2),
