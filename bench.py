@@ -283,7 +283,8 @@ def run_serve_workload(args):
 
     def serve(paced):
         arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
-        sv = J.Server(arena, precision=J.JEFI_PREC_F32_COMP, max_inflight=2, max_batch=256)
+        sv = J.Server(arena, precision=J.JEFI_PREC_F32_COMP, max_inflight=args.serve_inflight, max_batch=256,
+                      reserve_cus=args.serve_reserve_cus)
         for sp in specs:
             sv.open_session(sp["session"], grids[sp["session"]], sp["capacity"], sp["capacity"], 0.0, sp["dt"],
                             hist0[sp["session"]].astype(np.float32))
@@ -409,7 +410,8 @@ def run_serve_workload(args):
                                "(source edge log-U[8,48], observation edge log-U[8,64], ring 2 e_s + 8, one "
                                "new slice per request), HBM arena budget "
                                f"{arena_bytes/1e9:.0f} GB, FP32-compensated",
-                   "requests": len(reqs)},
+                   "requests": len(reqs), "batches_in_flight": args.serve_inflight,
+                   "reserve_cus": args.serve_reserve_cus},
         "served_req_per_s_back_to_back": round(len(reqs) / wall_o, 2),
         "paced": {"req_per_s": round(len(reqs) / wall_p, 2),
                   "latency_ms": {"p50": round(float(np.percentile(lat_p, 50)), 3),
@@ -735,6 +737,10 @@ def main():
                     help="comma-separated grid edges for --workload paper-steps (default 20,60,70,100,160)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the time-stencil variants of the headline workload")
+    ap.add_argument("--serve-inflight", type=int, default=2,
+                    help="serve workload: batches in flight at once (server streams)")
+    ap.add_argument("--serve-reserve-cus", type=int, default=0,
+                    help="serve workload: compute units each batch launch leaves free for the others")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the request stream for --workload serve")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

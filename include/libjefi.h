@@ -117,6 +117,10 @@ typedef struct {
   int32_t tile_config;   /* launch shape: 0 = automatic (autotuned table, else a size
                             heuristic), 1 = 8x8x8 observation tiles (512 threads),
                             2 = 8x8x4 tiles (256 threads) */
+  int32_t reserve_cus;   /* jefi_eval_batch only: the persistent launch leaves this many
+                            compute units' worth of workgroup slots free (at most half the
+                            device), so that launches on other streams can start while it
+                            runs; 0 (default) = every slot; 0 .. 1024, else EINVAL */
 } jefi_options;
 
 /* How the FP32 path reaches the canonical FP64 slice index of each pair
@@ -254,6 +258,9 @@ typedef struct {
   int32_t max_queue;        /* waiting requests before submit returns EBUSY (0 = 65536) */
   uint32_t flags;           /* jefi_options.flags of every evaluation (index mode, time-stencil
                                readings); 0 = defaults; invalid combinations: EINVAL at create */
+  int32_t reserve_cus;      /* jefi_options.reserve_cus of every batch: with max_inflight >= 3,
+                               small requests then start beside large ones instead of waiting
+                               for them (lower tail latency, some throughput); 0 = none */
 } jefi_server_config;
 
 typedef struct {

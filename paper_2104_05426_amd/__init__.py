@@ -57,7 +57,8 @@ class jefi_fields(C.Structure):
 
 class jefi_options(C.Structure):
     _fields_ = [("c", C.c_double), ("screen", C.c_double * 3), ("screen_set", C.c_int32),
-                ("precision", C.c_int32), ("flags", C.c_uint32), ("tile_config", C.c_int32)]
+                ("precision", C.c_int32), ("flags", C.c_uint32), ("tile_config", C.c_int32),
+                ("reserve_cus", C.c_int32)]
 
 
 class jefi_problem(C.Structure):
@@ -68,7 +69,7 @@ class jefi_problem(C.Structure):
 class jefi_server_config(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("pinned_bytes", C.c_uint64),
                 ("precision", C.c_int32), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
-                ("max_queue", C.c_int32), ("flags", C.c_uint32)]
+                ("max_queue", C.c_int32), ("flags", C.c_uint32), ("reserve_cus", C.c_int32)]
 
 
 class jefi_request(C.Structure):
@@ -292,11 +293,11 @@ class Server:
     ``arena``: a device tensor whose bytes the server may use."""
 
     def __init__(self, arena, precision=JEFI_PREC_F32_COMP, max_inflight=2, max_batch=256,
-                 max_queue=65536, pinned_bytes=0, flags=0):
+                 max_queue=65536, pinned_bytes=0, flags=0, reserve_cus=0):
         self.arena = arena
         cfg = jefi_server_config(_ptr(arena), arena.numel() * arena.element_size(), int(pinned_bytes),
                                  int(precision), int(max_inflight), int(max_batch), int(max_queue),
-                                 int(flags))
+                                 int(flags), int(reserve_cus))
         h = C.c_void_p()
         _check(lib.jefi_server_create(C.byref(cfg), C.byref(h)))
         self.h = h

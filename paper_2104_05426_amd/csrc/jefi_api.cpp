@@ -120,6 +120,7 @@ struct Resolved {
   int precision;
   int tile_config;
   unsigned flags;
+  int reserve_cus;
 };
 
 jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resolved* r) {
@@ -131,6 +132,8 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
     return fail(JEFI_EINVAL, "unknown precision %d", opt->precision);
   if (opt->tile_config < 0 || opt->tile_config > 2)
     return fail(JEFI_EINVAL, "tile_config %d (0 = auto, 1 = 8x8x8, 2 = 8x8x4)", opt->tile_config);
+  if (opt->reserve_cus < 0 || opt->reserve_cus > 1024)
+    return fail(JEFI_EINVAL, "reserve_cus %d (0 .. 1024)", opt->reserve_cus);
   const unsigned known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE |
                          JEFI_FLAG_PAST_HOLD | JEFI_FLAG_TIME_CUBIC;
   const unsigned idx = opt->flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE);
@@ -145,6 +148,7 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
   r->c = opt->c;
   r->precision = opt->precision;
   r->tile_config = opt->tile_config;
+  r->reserve_cus = opt->reserve_cus;
   for (int a = 0; a < 3; ++a) {
     if (opt->screen_set) {
       if (!std::isfinite(opt->screen[a]) || opt->screen[a] < 0.0)
@@ -539,7 +543,7 @@ struct BatchWorkspace {
   bool ev_used[2] = {false, false};
   int turn = 0;
   // graph per (is_f64, wz, index mode), valid for the current `dev` buffer
-  std::map<int, hipGraphExec_t> graphs;
+  std::map<long long, hipGraphExec_t> graphs;
   BatchDevice bd{};
 };
 std::mutex g_batch_mu;
@@ -555,13 +559,19 @@ void drop_graphs(BatchWorkspace& w) {
 int slots_per_cu(int wz) { return wz == 2 ? 2 : 4; }
 constexpr int kItemsPerSlot = 12;
 
-jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, int cub, hipGraphExec_t* out) {
-  hipGraph_t g;
-  hipError_t e = hipGraphCreate(&g, 0);
-  if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+// Compute units whose workgroup slots a persistent launch fills: all of
+// them less the caller's reserve, which is capped at half the device.
+int launch_cus(int reserve) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus - std::min(reserve, cus / 2);
+}
+
+jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, int cub, int cus, hipGraphExec_t* out) {
+  hipGraph_t g;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
   void* args[] = {&w.bd};
   hipKernelNodeParams kp{};
   kp.kernelParams = args;
@@ -619,6 +629,7 @@ void jefi_options_default(jefi_options* opt) {
   opt->precision = JEFI_PREC_F32_COMP;
   opt->flags = 0;
   opt->tile_config = 0;
+  opt->reserve_cus = 0;
 }
 
 uint64_t jefi_history_bytes(const jefi_grid* src, int32_t capacity, int32_t dtype) {
@@ -838,9 +849,12 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
 
   // Splits: equal-cost items, about kItemsPerSlot per workgroup slot, so
   // that the last items to finish leave little of the device idle.
-  int dev = 0, cus = 256;
+  int dev = 0;
   (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  // items are sized for the whole device, so that a reserve changes only how
+  // many workgroups run at once, not the decomposition (nor the results)
+  const int cus = launch_cus(0);
+  const int run_cus = launch_cus(cs[0].r.reserve_cus);  // the options are shared
   const int tile_pts = 64 * (tile_z == 8 ? 8 : 4);
   double total_cost = 0.0;
   for (int k = 0; k < nb; ++k) {
@@ -997,11 +1011,11 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
   }
   // one stencil for the whole batch (the options are shared)
   const int cub = nb > 0 && (params[0].stencil & kStencilCubic) ? 1 : 0;
-  const int gkey = cub * 16 + is_f64 * 8 + idx * 4 + wz;
+  const long long gkey = (long long)run_cus * 32 + cub * 16 + is_f64 * 8 + idx * 4 + wz;
   auto it = w.graphs.find(gkey);
   if (it == w.graphs.end()) {
     hipGraphExec_t ge;
-    jefi_status st = build_graph(w, is_f64, wz, idx, cub, &ge);
+    jefi_status st = build_graph(w, is_f64, wz, idx, cub, run_cus, &ge);
     if (st != JEFI_OK) return st;
     it = w.graphs.emplace(gkey, ge).first;
   }

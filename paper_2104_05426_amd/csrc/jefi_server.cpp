@@ -391,6 +391,7 @@ void admit_and_launch(jefi_server* sv) {
     jefi_options_default(&opt);
     opt.precision = sv->cfg.precision;
     opt.flags = sv->cfg.flags;
+    opt.reserve_cus = sv->cfg.reserve_cus;
     rc = jefi_eval_batch(probs.data(), (int32_t)probs.size(), &opt, st);
     if (rc == JEFI_EDEVICE) set_sticky(sv, hipErrorUnknown, jefi_last_error());
   }
@@ -474,6 +475,7 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
   const uint32_t slope_cubic = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
   if ((cfg->flags & ~known) != 0 || (cfg->flags & both) == both || (cfg->flags & slope_cubic) == slope_cubic)
     return JEFI_EINVAL;
+  if (cfg->reserve_cus < 0 || cfg->reserve_cus > 1024) return JEFI_EINVAL;
   jefi_server* sv = new jefi_server();
   sv->cfg = *cfg;
   if (sv->cfg.max_inflight < 1) sv->cfg.max_inflight = 2;

@@ -76,12 +76,13 @@ class BatchRun:
             self.E.append(torch.full((3, n), float("nan"), dtype=self.tdt, device="cuda"))
             self.B.append(torch.full((3, n), float("nan"), dtype=self.tdt, device="cuda"))
 
-    def options(self, tile=0, flags=0):
+    def options(self, tile=0, flags=0, reserve_cus=0):
         J = self.J
         pr = J.JEFI_PREC_F64 if self.prec == "f64" else J.JEFI_PREC_F32_COMP
         opt = J.jefi_options_default(precision=pr)
         opt.tile_config = tile
         opt.flags = flags
+        opt.reserve_cus = reserve_cus
         return opt
 
     def problem_structs(self):
@@ -89,12 +90,12 @@ class BatchRun:
         return [J.make_problem(p.src, h, p.dt, p.nt, p.obs, p.t, E, B)
                 for p, h, E, B in zip(self.problems, self.hists, self.E, self.B)]
 
-    def run_batch(self, tile=0, flags=0):
+    def run_batch(self, tile=0, flags=0, reserve_cus=0):
         import torch
         for E, B in zip(self.E, self.B):
             E.fill_(float("nan"))
             B.fill_(float("nan"))
-        self.J.jefi_eval_batch(self.problem_structs(), self.options(tile, flags))
+        self.J.jefi_eval_batch(self.problem_structs(), self.options(tile, flags, reserve_cus))
         torch.cuda.synchronize()
         return self.results()
 

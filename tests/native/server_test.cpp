@@ -275,6 +275,10 @@ void option_flags() {
   CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
   cfg.flags = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
   CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
+  cfg.flags = 0;
+  cfg.reserve_cus = -1;
+  CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
+  cfg.reserve_cus = 0;
   std::vector<char> ar;
   const uint32_t flags = JEFI_FLAG_PAST_HOLD | JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_INDEX_TABLE;
   jefi_server* sv = make_server(8 << 20, 2, 64, ar, flags);

@@ -56,7 +56,7 @@ def _grid(n=(4, 4, 4), h=0.1):
 @pytest.mark.parametrize("case", [
     "null-src", "bad-spacing", "nt-zero", "nt-over-capacity", "nt-over-pushed", "t-after-newest",
     "dtype-mismatch", "bad-c", "negative-screen", "null-out", "bad-dt", "bad-flags", "both-flags",
-    "slope-and-cubic", "bad-tile",
+    "slope-and-cubic", "bad-tile", "bad-reserve",
 ])
 def test_eval_validation(case):
     """Each bad input returns EINVAL with a message, before any device call."""
@@ -98,6 +98,8 @@ def test_eval_validation(case):
         opt.flags = J.JEFI_FLAG_INDEX_GUARD | J.JEFI_FLAG_INDEX_TABLE | J.JEFI_FLAG_PAST_HOLD
     elif case == "bad-tile":
         opt.tile_config = 3
+    elif case == "bad-reserve":
+        opt.reserve_cus = -1
     st = J.lib.jefi_eval_fields(src_p, C.byref(h), dt, nt, C.byref(obs), t, C.byref(fields),
                                 C.byref(opt), None)
     assert st == J.JEFI_EINVAL

@@ -101,6 +101,21 @@ def test_graph_replays_agree():
         del junk
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_cu_reserve_leaves_results_unchanged(prec):
+    """A persistent launch that leaves compute units free (reserve_cus) takes
+    the same items and reduces them in the same order: bitwise the same
+    results as the full launch, also for a reserve beyond half the device."""
+    G = _gpu()
+    probs = _small_batch(10, seed=8)
+    run = G.BatchRun(probs, prec)
+    full = run.run_batch()
+    for reserve in (32, 1024):
+        part = run.run_batch(reserve_cus=reserve)
+        for k, ((a, b), (c, d)) in enumerate(zip(full, part)):
+            assert np.array_equal(a, c) and np.array_equal(b, d), (prec, reserve, k)
+
+
 def test_batch_with_fallback_instances():
     """An empty observation grid, an evaluation time before every stencil
     and a long-window instance (dt << spacing) inside one batch."""
