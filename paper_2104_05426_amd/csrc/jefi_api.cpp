@@ -542,7 +542,7 @@ struct BatchWorkspace {
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_used[2] = {false, false};
   int turn = 0;
-  // graph per (is_f64, wz, index mode), valid for the current `dev` buffer
+  // graph per (launch width, cubic stencil, is_f64, index mode, wz), valid for the current `dev` buffer
   std::map<long long, hipGraphExec_t> graphs;
   BatchDevice bd{};
 };
