@@ -18,5 +18,6 @@ def test_help_lists_the_options():
     out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True,
                          text=True, timeout=120)
     assert out.returncode == 0
-    for opt in ("--gpus", "--steps", "--warmup", "--workload", "--no-variants", "--paper-sizes"):
+    for opt in ("--gpus", "--steps", "--warmup", "--workload", "--no-variants", "--paper-sizes",
+                "--serve-inflight", "--serve-reserve-cus"):
         assert opt in out.stdout, opt
