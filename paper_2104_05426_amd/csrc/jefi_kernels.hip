@@ -109,7 +109,7 @@ __device__ __forceinline__ float r2_f32(float dx, float dy, float dz) {
 template <class Canon>
 __device__ __forceinline__ void index_f32(float dx, float dy, float dz, float af, float halfg,
                                           Canon canon_fn, float& m, float& f, float& ri) {
-  // separations in units of c dt: R = r2 / sqrt(r2) lands in slice units
+  // separations in units of c dt: R = r2 * rsq(r2) is then in slice units
   float r2 = r2_f32(dx, dy, dz);
   ri = __builtin_amdgcn_rsqf(r2);
   float u = __builtin_fmaf(-r2, ri, af);
@@ -325,7 +325,8 @@ __device__ __forceinline__ void put_cubic(float4* lds, int PU, int idx, const D4
 // of LDS entry e.  Linear planes (h, S, D, T): value h + f S, derivative
 // D + f T (the derivative planes carry the time unit).  Cubic planes
 // (c0 .. c3): value and derivative in one Horner pass, the derivative in f
-// times dsc (1/dt in the caller's time unit).
+// times dsc (1/dt; c in the FP32 kernels, which measure time in steps and
+// lengths in c dt).
 template <bool CUB>
 __device__ __forceinline__ void entry_at(const float4* lds, int PU, int e, float f, float dsc, float v[4],
                                          float w[4]) {
