@@ -6,6 +6,7 @@ import os
 import pytest
 
 import oracle
+from tests import test_oracle_fingerprint as fpins
 from tests import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "jefi_oracle.c")
@@ -83,3 +84,52 @@ def test_planted_mistake_is_caught(name, tmp_path):
     finally:
         oracle._use_library(None)
     assert failures >= 1, f"no pin caught: {name}"
+
+
+# Mistakes in the per-point fingerprint of the slice decisions; caught by the
+# fingerprint pins (hand-computed rows, rows rebuilt from the pure-Python
+# per-pair decisions).
+FP_MUTATIONS = {
+    "fingerprint drops pairs at k = -1": ("if (k < -1) continue;\n      ++nlive;",
+                                          "if (k <= -1) continue;\n      ++nlive;"),
+    "fingerprint counts pairs at k = -2": ("if (k < -1) continue;\n      ++nlive;",
+                                           "if (k < -2) continue;\n      ++nlive;"),
+    "fingerprint weights by s instead of s+1": ("skw += (uint64_t)k * (uint64_t)(s + 1);",
+                                                "skw += (uint64_t)k * (uint64_t)s;"),
+    "fingerprint does not count screened pairs": ("{ ++nscr; continue; }", "{ continue; }"),
+    "fingerprint ignores the point selection": (
+        "int64_t o = sel ? sel[q] : q;\n    if (o < 0 || o >= no) { bad = 1; continue; }\n    double ro[3];\n"
+        "    orc_centre(obs, o, ro);\n    int64_t nlive",
+        "int64_t o = q;\n    if (o < 0 || o >= no) { bad = 1; continue; }\n    double ro[3];\n"
+        "    orc_centre(obs, o, ro);\n    int64_t nlive"),
+}
+
+FP_PIN_CALLS = [
+    fpins.test_hand_computed_fingerprints,
+    fpins.test_hand_computed_fingerprint_off_slice_and_screening_cube,
+    lambda: fpins.test_fingerprint_equals_the_pure_python_pair_decisions(0),
+    lambda: fpins.test_fingerprint_equals_the_pure_python_pair_decisions(1),
+    fpins.test_negative_indices_wrap_the_weighted_sum,
+]
+
+
+@pytest.mark.parametrize("name", sorted(FP_MUTATIONS))
+def test_planted_fingerprint_mistake_is_caught(name, tmp_path):
+    old, new = FP_MUTATIONS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, f"mutation anchor not found once: {old}"
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(text.replace(old, new))
+    lib = str(tmp_path / "libmutant.so")
+    oracle.build(source=str(mutated), target=lib)
+    failures = 0
+    oracle._use_library(lib)
+    try:
+        for call in FP_PIN_CALLS:
+            try:
+                call()
+            except (AssertionError, ValueError):
+                failures += 1
+    finally:
+        oracle._use_library(None)
+    assert failures >= 1, f"no fingerprint pin caught: {name}"
