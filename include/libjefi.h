@@ -317,7 +317,8 @@ jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t
  * ticket is then released), res filled either way.  ENOENT: unknown ticket. */
 jefi_status jefi_server_poll(jefi_server* sv, uint64_t ticket, jefi_result* res);
 
-/* Blocks until the ticket is done (one waiter per ticket), then as poll. */
+/* Blocks until the ticket is done, then as poll.  If another thread polls
+ * or waits the same ticket and releases it first, returns ENOENT. */
 jefi_status jefi_server_wait(jefi_server* sv, uint64_t ticket, jefi_result* res);
 
 /* Frees an idle session's ring.  EBUSY while it has queued or running requests. */

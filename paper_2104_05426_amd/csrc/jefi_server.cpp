@@ -283,8 +283,9 @@ void admit_and_launch(jefi_server* sv) {
       continue;
     }
     in_batch.insert(s.id);
+    bool fresh = false;  // ring uploaded on `st` in this pass
+    Region stg{true, 0, 0};
     if (!s.resident) {
-      Region stg;
       jefi_status rc = materialise(sv, s, st, in_batch, &stg);
       if (stg.bytes) b.extra.push_back(stg);
       if (rc != JEFI_OK) {
@@ -292,6 +293,7 @@ void admit_and_launch(jefi_server* sv) {
         if (rc == JEFI_EDEVICE) return;
         break;  // no room yet: wait for completions
       }
+      fresh = true;
     }
     const uint64_t slice_bytes = r.slice.size();
     const uint64_t out_bytes = r.out_on_host ? (uint64_t)6 * r.n_obs * (r.out_dtype == JEFI_F64 ? 8 : 4) : 0;
@@ -306,6 +308,21 @@ void admit_and_launch(jefi_server* sv) {
     if (!ok) {
       release_req(sv, r);
       in_batch.erase(s.id);
+      if (fresh) {
+        // The ring upload is queued on `st` but the session joins no batch
+        // here: its next request may run on another stream, with nothing
+        // ordering it after the upload (nor its eviction after it).  Let the
+        // upload finish before the session is used again.
+        const hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+          set_sticky(sv, e, "session upload");
+          return;
+        }
+        if (stg.bytes) {
+          sv->darena.release(stg.off, stg.bytes);
+          b.extra.pop_back();
+        }
+      }
       break;
     }
     (void)el;
@@ -636,6 +653,7 @@ jefi_status jefi_server_poll(jefi_server* sv, uint64_t ticket, jefi_result* res)
   fill_result(it->second, res);
   if (it->second.state != kDone) return JEFI_PENDING;
   sv->reqs.erase(it);
+  sv->done_cv.notify_all();  // a waiter on the same ticket now sees it gone
   return JEFI_OK;
 }
 
@@ -644,8 +662,13 @@ jefi_status jefi_server_wait(jefi_server* sv, uint64_t ticket, jefi_result* res)
   std::unique_lock<std::mutex> lk(sv->mu);
   auto it = sv->reqs.find(ticket);
   if (it == sv->reqs.end()) return JEFI_ENOENT;
-  sv->done_cv.wait(lk, [&]() { return sv->reqs[ticket].state == kDone; });
+  // another thread may poll or wait the same ticket and release it first
+  sv->done_cv.wait(lk, [&]() {
+    const auto f = sv->reqs.find(ticket);
+    return f == sv->reqs.end() || f->second.state == kDone;
+  });
   it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return JEFI_ENOENT;
   fill_result(it->second, res);
   sv->reqs.erase(it);
   return JEFI_OK;

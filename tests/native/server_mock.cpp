@@ -68,7 +68,8 @@ struct MockEvent {
   uint64_t recorded = 0, done = 0;
 };
 
-int g_eval_sleep_us = 0;  // set by the test to keep batches on the "device" longer
+int g_eval_sleep_us = 0;    // set by the test to keep batches on the "device" longer
+int g_ingest_sleep_us = 0;  // likewise for ring uploads (re-materialisation)
 
 hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipGetDevice(int* d) {
@@ -230,7 +231,11 @@ namespace jefi {
 hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, int, int, int n_slots, int is_f64,
                                hipStream_t s) {
   const size_t bytes = (size_t)n_slots * 4 * (size_t)src.n[0] * src.n[1] * src.n[2] * (is_f64 ? 8 : 4);
-  s->push([hist, ring, bytes]() { std::memcpy(ring, hist, bytes); });
+  const int sleep_us = g_ingest_sleep_us;
+  s->push([hist, ring, bytes, sleep_us]() {
+    if (sleep_us) std::this_thread::sleep_for(std::chrono::microseconds(sleep_us));
+    std::memcpy(ring, hist, bytes);
+  });
   return hipSuccess;
 }
 }  // namespace jefi

@@ -15,6 +15,7 @@
 #include "../../include/libjefi.h"
 
 extern int g_eval_sleep_us;
+extern int g_ingest_sleep_us;
 extern std::atomic<unsigned> g_last_batch_flags;
 
 static std::atomic<int> g_fail{0};
@@ -303,6 +304,90 @@ void option_flags() {
   CHECK(jefi_server_destroy(sv2) == JEFI_OK);
 }
 
+// A session brought back into the arena in a pass whose request then does
+// not fit (its slice finds no room) must not be used on another stream
+// before its ring upload has finished.  Two streams; the first-fit arena of
+// 312000 B is laid out as follows (rings of 4^3-cell sessions: 6144 B, of
+// the 10^3-cell session B: 96000 B, as much again to stage its shadow):
+//   - sessions B, A, C, G open in that order: rings at 0, 96000, 102144,
+//     108288;
+//   - G's request takes its slice and 192000 B of outputs at 114432;
+//   - C's request (outputs 81152 B) finds no room at the end and evicts B,
+//     the least recently used idle session: its outputs go to 0;
+//   - A and B queue while G and C run.  When G completes, one pass admits A
+//     and brings B back into G's old region (ring and shadow staging), but
+//     B's slice (16128 B) fits nowhere, also after evicting the idle G: the
+//     batch holds A only, and B's (slow) ring upload is queued on its stream;
+//   - when C completes, B's request runs on C's stream.
+// B's result is right only if its push and evaluation follow the upload.
+void materialised_but_not_admitted() {
+  std::vector<char> arena;
+  jefi_server* sv = make_server(312000, 2, 64, arena);
+  g_eval_sleep_us = 20000;
+  g_ingest_sleep_us = 0;
+  std::vector<Session> ss = {{51, 10, 0}, {52, 4, 0}, {53, 4, 0}, {54, 4, 0}};  // B A C G
+  open_sessions(sv, ss, 3);
+  Session &B = ss[0], &A = ss[1], &C = ss[2], &G = ss[3];
+  Pending pg, pc, pa, pb;
+  submit(sv, G, pg, 20);  // 8000 points: 192000 B of outputs
+  std::this_thread::sleep_for(std::chrono::milliseconds(8));
+  submit(sv, C, pc, 15);  // 3375 points: 81152 B
+  std::this_thread::sleep_for(std::chrono::milliseconds(4));
+  g_ingest_sleep_us = 40000;
+  submit(sv, A, pa, 1);
+  submit(sv, B, pb, 1);
+  check_result(sv, pg);
+  check_result(sv, pc);
+  check_result(sv, pa);
+  check_result(sv, pb);
+  g_ingest_sleep_us = 0;
+  jefi_server_stats st;
+  CHECK(jefi_server_get_stats(sv, &st) == JEFI_OK);
+  CHECK(st.evictions >= 2 && st.rematerialisations >= 1 && st.batches == 4);
+  std::printf("materialised but not admitted: %llu evictions, %llu rematerialisations, %llu batches\n",
+              (unsigned long long)st.evictions, (unsigned long long)st.rematerialisations,
+              (unsigned long long)st.batches);
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
+// One ticket polled and waited from two threads: exactly one of them takes
+// the result, the other sees the ticket gone; neither blocks forever.
+void poll_and_wait_one_ticket() {
+  std::vector<char> arena;
+  jefi_server* sv = make_server(8 << 20, 2, 64, arena);
+  g_eval_sleep_us = 5000;
+  std::vector<Session> ss = {{61, 3, 0}};
+  open_sessions(sv, ss, 2);
+  for (int round = 0; round < 20; ++round) {
+    Pending p;
+    submit(sv, ss[0], p, 1);
+    std::atomic<int> ok{0}, gone{0};
+    std::thread waiter([&]() {
+      jefi_result res;
+      const jefi_status st = jefi_server_wait(sv, p.ticket, &res);
+      if (st == JEFI_OK) ok++;
+      else if (st == JEFI_ENOENT) gone++;
+    });
+    std::thread poller([&]() {
+      jefi_result res;
+      for (;;) {
+        const jefi_status st = jefi_server_poll(sv, p.ticket, &res);
+        if (st == JEFI_PENDING) {
+          std::this_thread::sleep_for(std::chrono::microseconds(100));
+          continue;
+        }
+        if (st == JEFI_OK) ok++;
+        else if (st == JEFI_ENOENT) gone++;
+        break;
+      }
+    });
+    waiter.join();
+    poller.join();
+    CHECK(ok.load() == 1 && gone.load() == 1);
+  }
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
 }  // namespace
 
 int main() {
@@ -312,6 +397,8 @@ int main() {
   full_queue_and_rejections();
   time_after_newest_fails_at_admission();
   option_flags();
+  materialised_but_not_admitted();
+  poll_and_wait_one_ticket();
   if (g_fail.load() == 0) std::printf("server ok\n");
   return g_fail.load() == 0 ? 0 : 1;
 }

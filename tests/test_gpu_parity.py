@@ -3,7 +3,8 @@
 Bars: the slice index is bit-exact (per-pair dumps on small problems,
 per-point fingerprints taken by the field kernel itself on larger ones);
 E and B agree per component in relative L2 within 1e-12 (FP64 path) and
-1e-5 (FP32 compensated path)."""
+1e-5 (FP32 compensated path), and at every point within ten times that of
+the component's largest value."""
 import math
 
 import numpy as np
@@ -11,7 +12,7 @@ import pytest
 
 import oracle
 import workloads
-from oracle.compare import rel_l2
+from oracle.compare import check_fields, rel_l2
 from workloads import Grid, Problem, blob_history, centred_grid, Blob
 
 pytestmark = pytest.mark.gpu
@@ -57,11 +58,9 @@ def _large():
 
 
 def _assert_fields(Eg, Bg, Er, Br, tol, label=""):
-    e, fe = rel_l2(Eg, Er)
-    b, fb = rel_l2(Bg, Br)
-    print(f"{label} rel L2 E={['%.2e' % x for x in e]} B={['%.2e' % x for x in b]}", flush=True)
-    assert np.all(np.isfinite(Eg)) and np.all(np.isfinite(Bg))
-    assert max(e + b) <= tol, (e, b)
+    """Relative L2 per component <= tol and every point within 10 tol of
+    its component's largest value."""
+    check_fields(Eg, Bg, Er, Br, tol, label or "fields")
 
 
 @pytest.mark.parametrize("tile", [1, 2])

@@ -3,7 +3,9 @@ host compiler against a host mock of the HIP runtime and of the library
 calls (tests/native/server_mock.cpp), under ThreadSanitizer and under
 AddressSanitizer + UBSan.  Concurrent submitters, overlapping batches with
 per-session ordering, eviction and re-materialisation, a full queue,
-rejections, session closing and timestamps (tests/native/server_test.cpp)."""
+rejections, session closing and timestamps, a session brought back into the
+arena in a pass that cannot admit its request, and one ticket polled and
+waited from two threads (tests/native/server_test.cpp)."""
 import os
 import shutil
 import subprocess
