@@ -198,6 +198,22 @@ jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, dou
                              const jefi_grid* obs, double t, const jefi_fields* out,
                              const jefi_options* opt, void* stream);
 
+/* jefi_eval_fields for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid it).
+ * Same arguments, same validation and errors; it calls no hipMalloc or
+ * hipFree.  Its scratch (threshold table and FP64 split partials) is one
+ * fixed array of 128 MiB per GPU inside the library, held until the
+ * process ends.  The split count is that of jefi_eval_fields, capped so the
+ * partials fit (one split needs none), so the fields agree with
+ * jefi_eval_fields within the stated tolerances (not bit for bit when the
+ * cap applies); ETOOLARGE if a plan would still not fit.  Every call on a
+ * GPU shares that array, and nothing in it needs to start at zero: calls
+ * that overlap on one GPU (several streams or threads) race and must be
+ * serialised by the caller. */
+jefi_status jefi_eval_fields_noalloc(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt,
+                                     const jefi_grid* obs, double t, const jefi_fields* out,
+                                     const jefi_options* opt, void* stream);
+
 /* ---- batched evaluation (row: batched persistent launch) -------------------
  * Many independent problems of uneven sizes in one persistent launch:
  * workgroups pull (problem, observation tile, source split) items, heaviest

@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE"
 # Every function the header declares (the CPU tests check the exports).
 EXPORTS = [
     "jefi_version", "jefi_last_error", "jefi_options_default", "jefi_history_bytes",
-    "jefi_history_init", "jefi_history_push", "jefi_eval_fields", "jefi_slice_index_dump",
+    "jefi_history_init", "jefi_history_push", "jefi_eval_fields", "jefi_eval_fields_noalloc",
+    "jefi_slice_index_dump",
     "jefi_slice_fingerprint", "jefi_eval_batch", "jefi_autotune",
     "jefi_server_create", "jefi_server_open_session", "jefi_server_submit", "jefi_server_poll",
     "jefi_server_wait", "jefi_server_close_session", "jefi_server_get_stats", "jefi_server_destroy",
@@ -106,6 +107,8 @@ def _load():
         "jefi_history_push": ([P(jefi_history), P(jefi_grid), vp, vp], C.c_int),
         "jefi_eval_fields": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32, P(jefi_grid),
                               C.c_double, P(jefi_fields), P(jefi_options), vp], C.c_int),
+        "jefi_eval_fields_noalloc": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32, P(jefi_grid),
+                                      C.c_double, P(jefi_fields), P(jefi_options), vp], C.c_int),
         "jefi_slice_index_dump": ([P(jefi_grid), C.c_int32, C.c_double, C.c_int64, C.c_double,
                                    P(jefi_grid), C.c_double, P(jefi_options), vp, vp], C.c_int),
         "jefi_slice_fingerprint": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32,
@@ -223,6 +226,20 @@ def jefi_eval_fields(src, h: jefi_history, dt: float, nt: int, obs, t: float, E,
     _check(lib.jefi_eval_fields(C.byref(make_grid(src)), C.byref(h), float(dt), int(nt),
                                 C.byref(make_grid(obs)), float(t), C.byref(f),
                                 C.byref(opt) if opt is not None else None, _stream_ptr(stream)))
+
+
+def jefi_eval_fields_noalloc(src, h: jefi_history, dt: float, nt: int, obs, t: float, E, B,
+                             opt: Optional[jefi_options] = None, stream=None) -> None:
+    """As jefi_eval_fields, with the library's fixed device scratch: no
+    device memory is allocated.  Calls that overlap on one GPU race."""
+    import torch
+    dt_out = JEFI_F64 if E.dtype == torch.float64 else JEFI_F32
+    if B.dtype != E.dtype:
+        raise ValueError("E and B must share a dtype")
+    f = jefi_fields(_ptr(E), _ptr(B), dt_out)
+    _check(lib.jefi_eval_fields_noalloc(C.byref(make_grid(src)), C.byref(h), float(dt), int(nt),
+                                        C.byref(make_grid(obs)), float(t), C.byref(f),
+                                        C.byref(opt) if opt is not None else None, _stream_ptr(stream)))
 
 
 def jefi_slice_index_dump(src, nt: int, dt: float, newest: int, t0: float, obs, t: float, out,

@@ -734,6 +734,67 @@ jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, dou
   return JEFI_OK;
 }
 
+jefi_status jefi_eval_fields_noalloc(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt,
+                                     const jefi_grid* obs, double t, const jefi_fields* out,
+                                     const jefi_options* opt, void* stream) {
+  if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
+  if (!out) return fail(JEFI_EINVAL, "output fields are NULL");
+  Checked c;
+  {
+    jefi_status st = check_problem(src, hist, dt, nt, obs, t, out, opt, 0, 0, &c);
+    if (st != JEFI_OK) return st;
+    const int tz = c.plan.p.tile_z;
+    // the split count of jefi_eval_fields, capped so that the FP64 split
+    // partials fit the fixed scratch behind the threshold table (one split
+    // needs none: the pair kernel then writes E and B itself)
+    long long target = single_target_wg(tz);
+    if (c.no > 0 && c.plan.p.n_tiles > 0) {
+      const unsigned long long room = kNoAllocScratchBytes - kThrBytes;
+      const long long fit = (long long)(room / (6ull * sizeof(double) * (unsigned long long)c.no));
+      target = std::min(target, std::max(fit, 1LL) * (long long)c.plan.p.n_tiles);
+    }
+    st = check_problem(src, hist, dt, nt, obs, t, out, opt, target, tz, &c);
+    if (st != JEFI_OK) return st;
+  }
+  if (c.no == 0) return JEFI_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int out_f64 = out->dtype == JEFI_F64;
+  if (c.ns == 0 || c.plan.all_dead) {
+    hipError_t e = launch_fill_zero_fields(out->E, out->B, c.no, out_f64, s);
+    return e == hipSuccess ? JEFI_OK : hip_fail(e, "zero-fill launch");
+  }
+  PairParams& p = c.plan.p;
+  attach_history(p, hist, nt);
+  p.E = out->E;
+  p.B = out->B;
+  p.out_f64 = out_f64;
+  p.direct = p.n_splits == 1;
+  const unsigned long long part_bytes = p.direct ? 0ull : (unsigned long long)p.n_splits * 6ull * (unsigned long long)c.no * sizeof(double);
+  if (kThrBytes + part_bytes > kNoAllocScratchBytes)
+    return fail(JEFI_ETOOLARGE, "%d splits x %lld points need %llu scratch bytes; the fixed scratch has %llu",
+                p.n_splits, c.no, (unsigned long long)(kThrBytes + part_bytes), kNoAllocScratchBytes);
+  void* base = nullptr;
+  hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
+  if (!p.direct) p.partial = (double*)((char*)base + kThrBytes);
+  if (c.r.precision == JEFI_PREC_F32_COMP && !c.plan.multi && p.use_thr) {
+    // rebuilt on every call: another call may have left its own table here
+    p.thr = (double*)base;
+    e = launch_thresholds(p.thr, p.thr_lo, p.thr_n, p.a_f, p.inv_cdt, s);
+    if (e != hipSuccess) return hip_fail(e, "threshold kernel launch");
+  } else {
+    p.use_thr = 0;
+  }
+  e = launch_pairs(p, c.r.precision == JEFI_PREC_F64, 0, c.plan.multi, c.plan.wsel, s);
+  if (e != hipSuccess) return hip_fail(e, "pair kernel launch");
+  if (!p.direct) {
+    EpilogueParams ep{p.partial, p.n_splits, c.no, p.pref, out->E, out->B, out_f64};
+    e = launch_epilogue(ep, s);
+    if (e != hipSuccess) return hip_fail(e, "epilogue launch");
+  }
+  return JEFI_OK;
+}
+
 jefi_status jefi_slice_index_dump(const jefi_grid* src, int32_t nt, double dt, int64_t newest, double t0,
                                   const jefi_grid* obs, double t, const jefi_options* opt, int32_t* out,
                                   void* stream) {

@@ -129,4 +129,10 @@ hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);
 hipError_t launch_fill_zero_fields(void* E, void* B, long long n_obs, int out_f64, hipStream_t s);
 hipError_t launch_dump(const DumpParams& p, hipStream_t s);
 
+// Fixed device scratch of the allocation-free evaluation (per GPU): the
+// threshold table and FP64 split partials.
+constexpr unsigned long long kNoAllocScratchBytes = 128ull << 20;
+// Address of the current device's copy (looked up on its first use).
+hipError_t noalloc_scratch(void** out);
+
 }  // namespace jefi

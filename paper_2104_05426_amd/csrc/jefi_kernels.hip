@@ -30,6 +30,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "jefi_internal.h"
 
@@ -1752,5 +1754,31 @@ hipError_t launch_dump(const DumpParams& p, hipStream_t s) {
   hipLaunchKernelGGL(dump_kernel, dim3(grid_for(ns * no, 256)), dim3(256), 0, s, p);
   return hipGetLastError();
 }
+
+// Scratch of the allocation-free evaluation: one fixed array per GPU, held
+// until the process ends.  Host code never uses the array's name as an
+// address: each device's copy is looked up once, with that device current,
+// and that address is what kernels receive.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> by_device;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = by_device.find(dev);
+  if (it == by_device.end()) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (ptr == nullptr) return hipErrorInvalidSymbol;
+    it = by_device.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
 
 }  // namespace jefi
