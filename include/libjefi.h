@@ -115,8 +115,11 @@ typedef struct {
                             JEFI_FLAG_PAST_HOLD; other bits and combinations are
                             rejected (EINVAL) */
   int32_t tile_config;   /* launch shape: 0 = automatic (autotuned table, else a size
-                            heuristic), 1 = 8x8x8 observation tiles (512 threads),
-                            2 = 8x8x4 tiles (256 threads) */
+                            rule: 8x8x8 tiles from 32768 observation points on, taken
+                            over the mean problem of a batch), 1 = 8x8x8 observation
+                            tiles (512 threads), 2 = 8x8x4 tiles (256 threads), 3 = the
+                            size rule per problem (a batch of large and small problems
+                            then runs one persistent launch per tile) */
   int32_t reserve_cus;   /* jefi_eval_batch only: the persistent launch leaves this many
                             compute units' worth of workgroup slots free (at most half the
                             device), so that launches on other streams can start while it
@@ -240,12 +243,31 @@ typedef struct {
  * for the upload of the call before last on the same stream. */
 jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream);
 
-/* Autotuner: times each launch shape on `probs` (one problem = single
- * launch, several = batch), `reps` runs each after a warm-up, records the
- * fastest for this size class (precision, log2 observation points per
- * problem, log2 total pairs) so tile_config = 0 uses it, and persists the
- * table to the file named by $JEFI_TUNE_CACHE when set.  Writes the outputs
- * of the problems.  best_config / best_ms may be NULL. */
+/* Autotuner.  A launch configuration is an observation tile (8x8x8 or
+ * 8x8x4), an FP32 slice-index mode (guard band or threshold table: the
+ * same indices, different speed) and a work granularity (half, default or
+ * twice the workgroup target of a single launch; 6, 12 or 24 work items per
+ * workgroup slot of a batch).  Every trial is `reps` timed runs after a
+ * warm-up on `stream`; the problems' outputs are written.
+ *   n == 1: times every configuration the problem admits (the 8x8x4 tile
+ *     only with 32-slot windows) and records the fastest for its size
+ *     class: precision, staging window class (32, 64 or 128 slots per cell,
+ *     or chunked), log2 observation points, log2 pairs.
+ *   n > 1: a greedy search from the untuned batch: each size class of
+ *     instances, heaviest first, tries the other tile (instances of one
+ *     batch may then run in two persistent launches, one per tile); then
+ *     the batch tries both index modes and the other granularities.  A
+ *     change is kept when it is at least 1 % faster.  Records the tile per
+ *     instance size class (within batches) and the batch's index mode and
+ *     granularity for its class (precision, log2 instances, log2 pairs).
+ * tile_config = 0 then uses the table (JEFI_FLAG_INDEX_* flags still fix
+ * the index mode); the table persists in the file named by
+ * $JEFI_TUNE_CACHE when that is set.  best_config = the chosen
+ * configuration (the batch-level one for n > 1) packed as
+ * tile | index mode << 2 | granularity << 4 (tile 1 = 8x8x8, 2 = 8x8x4,
+ * 0 = size rule; index 1 = guard, 2 = table, 0 = estimated; granularity
+ * 0 = default, 1 = coarser, 2 = finer); best_ms = its time per run.
+ * Either may be NULL. */
 jefi_status jefi_autotune(const jefi_problem* probs, int32_t n, const jefi_options* opt, int32_t reps,
                           void* stream, int32_t* best_config, double* best_ms);
 

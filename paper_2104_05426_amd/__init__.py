@@ -276,7 +276,9 @@ def jefi_eval_batch(problems, opt: Optional[jefi_options] = None, stream=None) -
 
 
 def jefi_autotune(problems, opt: Optional[jefi_options] = None, reps: int = 3, stream=None):
-    """Time the launch shapes on `problems`; returns (best tile_config, ms)."""
+    """Tune the launch configuration on `problems` (one: a single launch,
+    several: a batch); returns (packed configuration, ms per run): tile
+    | index mode << 2 | granularity << 4."""
     arr = (jefi_problem * len(problems))(*problems)
     best = C.c_int32(0)
     ms = C.c_double(0.0)

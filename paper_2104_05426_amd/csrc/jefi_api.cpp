@@ -130,8 +130,9 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
   if (!std::isfinite(opt->c) || !(opt->c > 0.0)) return fail(JEFI_EINVAL, "c must be finite and > 0");
   if (opt->precision != JEFI_PREC_F64 && opt->precision != JEFI_PREC_F32_COMP)
     return fail(JEFI_EINVAL, "unknown precision %d", opt->precision);
-  if (opt->tile_config < 0 || opt->tile_config > 2)
-    return fail(JEFI_EINVAL, "tile_config %d (0 = auto, 1 = 8x8x8, 2 = 8x8x4)", opt->tile_config);
+  if (opt->tile_config < 0 || opt->tile_config > 3)
+    return fail(JEFI_EINVAL, "tile_config %d (0 = auto, 1 = 8x8x8, 2 = 8x8x4, 3 = size rule per problem)",
+                opt->tile_config);
   if (opt->reserve_cus < 0 || opt->reserve_cus > 1024)
     return fail(JEFI_EINVAL, "reserve_cus %d (0 .. 1024)", opt->reserve_cus);
   const unsigned known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE |
@@ -161,17 +162,45 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
   return JEFI_OK;
 }
 
-// ---- launch-shape table (filled by the autotuner) --------------------------
-// Key: precision, log2 bucket of observation points per instance, log2
-// bucket of total pairs.  Value: tile_config (1 = 8x8x8, 2 = 8x8x4).
+// ---- launch configurations (table filled by the autotuner) -----------------
+// A launch configuration: observation tile (1 = 8x8x8, 2 = 8x8x4, 0 = the
+// size rule), FP32 index mode (0 = from the guard-pair estimate, 1 = guard
+// band, 2 = threshold table for every pair of a full brick) and work
+// granularity (0 = default, 1 = coarser, 2 = finer: half or twice the
+// workgroup target of a single launch, or 6 or 24 instead of 12 work items
+// per workgroup slot of a batch).
+struct LaunchCfg {
+  int tile = 0, idx = 0, gran = 0;
+};
+int cfg_pack(const LaunchCfg& c) { return c.tile | (c.idx << 2) | (c.gran << 4); }
+LaunchCfg cfg_unpack(int v) {
+  LaunchCfg c;
+  c.tile = v & 3;
+  c.idx = (v >> 2) & 3;
+  c.gran = (v >> 4) & 3;
+  return c;
+}
+bool cfg_valid(int v) {
+  const LaunchCfg c = cfg_unpack(v);
+  return v >= 0 && v < 64 && c.tile <= 2 && c.idx <= 2 && c.gran <= 2;
+}
+
+// Table keys (a kind tag in bits 40..): one problem launched alone, one
+// instance inside a batch, a whole batch.  The size class of a problem is
+// its precision, staging window class (32, 64 or 128 slots per cell, or
+// chunked), log2 of its observation points and log2 of its pairs; that of
+// a batch is its precision, log2 of its instance count and log2 of its
+// pairs.
+enum { kKeySingle = 1, kKeyMember = 2, kKeyBatch = 3 };
 std::mutex g_tune_mu;
 std::map<long long, int> g_tune;
 bool g_tune_loaded = false;
 
 int log2_bucket(double v) { return v < 1.0 ? 0 : (int)std::floor(std::log2(v)); }
 
-long long tune_key(int precision, double obs_per_inst, double pairs) {
-  return ((long long)precision << 16) | ((long long)log2_bucket(obs_per_inst) << 8) | log2_bucket(pairs);
+long long size_key(int kind, int precision, int wcls, double a, double b) {
+  return ((long long)kind << 40) | ((long long)precision << 32) | ((long long)wcls << 24) |
+         ((long long)log2_bucket(a) << 12) | (long long)log2_bucket(b);
 }
 
 const char* tune_path() {
@@ -189,7 +218,7 @@ void tune_load_locked() {
   long long k;
   int v;
   while (std::fscanf(f, "%lld %d", &k, &v) == 2)
-    if (v == 1 || v == 2) g_tune[k] = v;
+    if ((k >> 40) >= kKeySingle && (k >> 40) <= kKeyBatch && cfg_valid(v)) g_tune[k] = v;
   std::fclose(f);
 }
 
@@ -202,18 +231,25 @@ void tune_store_locked() {
   std::fclose(f);
 }
 
-int lookup_tile(int precision, double obs_per_inst, double pairs) {
+LaunchCfg lookup_cfg(long long key) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
-  auto it = g_tune.find(tune_key(precision, obs_per_inst, pairs));
-  return it == g_tune.end() ? 0 : it->second;
+  auto it = g_tune.find(key);
+  return it == g_tune.end() ? LaunchCfg{} : cfg_unpack(it->second);
 }
 
-// tile_z for a requested config: the tuned table first, else small
-// observation grids take the 256-thread 8x8x4 tile.
-int choose_tile_z(int tile_config, int precision, double obs_per_inst, double pairs) {
-  int cfg = tile_config;
-  if (cfg == 0) cfg = lookup_tile(precision, obs_per_inst, pairs);
+void store_cfgs(const std::vector<std::pair<long long, LaunchCfg>>& entries) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  for (const auto& e : entries) g_tune[e.first] = cfg_pack(e.second);
+  tune_store_locked();
+}
+
+// Observation tile edge in z: the caller's tile_config, else the tuned
+// tile, else the size rule (small observation grids take the 256-thread
+// 8x8x4 tile); tile_config 3 asks for the size rule.
+int choose_tile_z(int tile_config, int tuned_tile, double obs_per_inst) {
+  int cfg = tile_config == 3 ? 0 : tile_config ? tile_config : tuned_tile;
   if (cfg == 0) cfg = obs_per_inst >= 32768.0 ? 1 : 2;
   return cfg == 1 ? 8 : 4;
 }
@@ -276,6 +312,29 @@ bool guard_pairs_common(const jefi_grid* src, const jefi_grid* obs, const TimeSp
 }
 
 constexpr long long kMinRounds = 32;
+
+// Source splits of a single launch for a target workgroup count.
+void apply_splits(Plan* plan, int precision, long long splits_target_wg) {
+  PairParams& p = plan->p;
+  long long splits = (splits_target_wg + p.n_tiles - 1) / p.n_tiles;
+  // at least kMinRounds staging rounds per workgroup, so that its set-up
+  // (tile geometry, threshold table, first window) stays small
+  const int w = plan->multi ? 32 : plan->wsel;
+  long long g = (long long)(precision == JEFI_PREC_F64 ? 1 : 2) * (p.tile_z == 8 ? 2 : 1) * 32 / w;
+  if (g < 1) g = 1;
+  long long max_splits = p.n_bricks / (kMinRounds * g);
+  if (max_splits < 1) max_splits = 1;
+  if (splits > max_splits) splits = max_splits;
+  if (splits < 1) splits = 1;
+  // a multiple of 8 splits lets the launch deal them round-robin over the
+  // 8 XCDs (balanced shares of the source); the last ones may be empty
+  if (splits >= 8) splits &= ~7LL;
+  long long bps = (p.n_bricks + splits - 1) / splits;
+  if (splits < 8) splits = (p.n_bricks + bps - 1) / bps;
+  p.n_splits = (int)splits;
+  p.bricks_per_split = (int)bps;
+  p.n_wg = (int)((long long)p.n_tiles * splits);
+}
 
 // Everything about a launch except the history pointer and outputs.
 // `splits_target_wg`: workgroups to aim for (single launches) or 0 to
@@ -353,19 +412,22 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   const double umax = ts.inv_cdt * rmax + 2.0;
   const double e_u = ts.inv_cdt * e_R + eps * (umax + 1.0);
   double g = 1.25 * e_u + 1e-7;
+  const bool f64 = r.precision == JEFI_PREC_F64;
   p.use_thr = 0;
-  if (!(g < 0.5)) {
-    g = 0.5;  // every pair then takes the FP64 path
-  } else {
-    // Guard-band pairs have floor(u64) in {N-1, N}, N the integer nearest
-    // u32; u is monotone in r2, so floor(u64) >= N iff r2 <= T(N), with T(N)
-    // the largest FP64 r2 whose canonical u reaches N.  A threshold kernel
-    // builds the table for every N the launch can meet.
+  if (!(g < 0.5)) g = 0.5;  // every FP32 pair then takes the FP64 path
+  if (f64 || g < 0.5) {
+    // Pairs whose position u lies near an integer N have floor(u64) in
+    // {N-1, N}; u is monotone in r2, so floor(u64) >= N iff r2 <= T(N), with
+    // T(N) the largest FP64 r2 whose canonical u reaches N.  A threshold
+    // kernel builds the table for every N the launch can meet.  The FP32
+    // kernels decide guard-band pairs (or every pair) by it; the FP64
+    // kernels decide every pair of a full brick by it, with no correctly
+    // rounded square root.
     const double ulow = std::floor(ts.a_f - rmax * ts.inv_cdt) - 2.0;
     if (ulow > -1e9) {
       const long long lo = (long long)ulow;
       const long long n = 1 - lo + 1;
-      if (n <= kThrMax) {
+      if (n <= (f64 ? kThrMax64 : kThrMax)) {
         p.use_thr = 1;
         p.thr_lo = (int)lo;
         p.thr_n = (int)n;
@@ -379,7 +441,7 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   p.near_slack = std::max(1e-12, 4.0 * e_coord);
   p.exact_idx = 0;
   const unsigned idx_mode = r.flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE);
-  if (p.use_thr && idx_mode != JEFI_FLAG_INDEX_GUARD)
+  if (!f64 && p.use_thr && idx_mode != JEFI_FLAG_INDEX_GUARD)
     p.exact_idx = idx_mode == JEFI_FLAG_INDEX_TABLE || guard_pairs_common(src, obs, ts, g) ? 1 : 0;
   // Longest slice window any brick can need (the 8x8x8 tile bounds both shapes).
   const double wb = std::floor((diam_t + diam_b) * ts.inv_cdt * (1.0 + 1e-12) + 2.0 * p.margin + 1e-6) + 3.0;
@@ -392,26 +454,7 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   plan->multi = plan->wsel == 0;
   if (plan->multi || plan->wsel > 32) set_tiles(p, obs, 8);  // those kernels run 8x8x8 tiles only
 
-  if (splits_target_wg > 0) {
-    long long splits = (splits_target_wg + p.n_tiles - 1) / p.n_tiles;
-    // at least kMinRounds staging rounds per workgroup, so that its set-up
-    // (tile geometry, threshold table, first window) stays small
-    const int w = plan->multi ? 32 : plan->wsel;
-    long long g = (long long)(r.precision == JEFI_PREC_F64 ? 1 : 2) * (p.tile_z == 8 ? 2 : 1) * 32 / w;
-    if (g < 1) g = 1;
-    long long max_splits = p.n_bricks / (kMinRounds * g);
-    if (max_splits < 1) max_splits = 1;
-    if (splits > max_splits) splits = max_splits;
-    if (splits < 1) splits = 1;
-    // a multiple of 8 splits lets the launch deal them round-robin over the
-    // 8 XCDs (balanced shares of the source); the last ones may be empty
-    if (splits >= 8) splits &= ~7LL;
-    long long bps = (p.n_bricks + splits - 1) / splits;
-    if (splits < 8) splits = (p.n_bricks + bps - 1) / bps;
-    p.n_splits = (int)splits;
-    p.bricks_per_split = (int)bps;
-    p.n_wg = (int)((long long)p.n_tiles * splits);
-  }
+  if (splits_target_wg > 0) apply_splits(plan, r.precision, splits_target_wg);
   return JEFI_OK;
 }
 
@@ -492,11 +535,13 @@ struct Checked {
   long long ns, no;
   Resolved r;
   Plan plan;
+  LaunchCfg cfg;  // the configuration the plan follows (single launches)
 };
 
+// Validation and a plan with the given observation tile edge in z.
 jefi_status check_problem(const jefi_grid* src, const jefi_history* hist, double dt, int nt,
                           const jefi_grid* obs, double t, const jefi_fields* out, const jefi_options* opt,
-                          long long splits_target_wg, int force_tile_z, Checked* c) {
+                          long long splits_target_wg, int tile_z, Checked* c) {
   if (!grid_ok(src, "source", &c->ns) || !grid_ok(obs, "observation", &c->no)) return JEFI_EINVAL;
   jefi_status st = check_history(hist, nt);
   if (st != JEFI_OK) return st;
@@ -511,10 +556,55 @@ jefi_status check_problem(const jefi_grid* src, const jefi_history* hist, double
   if (hist->dtype != want)
     return fail(JEFI_EINVAL, "precision %s needs a %s history",
                 c->r.precision == JEFI_PREC_F64 ? "F64" : "F32_COMP", want == JEFI_F64 ? "F64" : "F32");
-  const int tile_z = force_tile_z ? force_tile_z
-                                  : choose_tile_z(c->r.tile_config, c->r.precision, (double)c->no,
-                                                  (double)c->no * (double)c->ns);
+  c->cfg = LaunchCfg{};
   return make_plan(src, obs, nt, dt, hist->newest, hist->t0, t, c->r, tile_z, splits_target_wg, &c->plan);
+}
+
+// Window class of a plan: 0, 1, 2 = 32, 64, 128 staged slots per cell, 3 = chunked.
+int window_class(const Plan& pl) { return pl.multi ? 3 : pl.wsel == 32 ? 0 : pl.wsel == 64 ? 1 : 2; }
+
+// The FP32 index mode of a configuration, unless the caller's flags fix one
+// (both modes give identical slice indices; they differ in speed only).
+void apply_idx(const LaunchCfg& cfg, const Resolved& r, PairParams& p) {
+  if (cfg.idx == 0 || r.precision != JEFI_PREC_F32_COMP || !p.use_thr) return;
+  if (r.flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE)) return;
+  p.exact_idx = cfg.idx == 2 ? 1 : 0;
+}
+
+// Workgroups a single launch aims for: many waves of them over the 256 CUs,
+// so that the cheap tiles (mostly culled) and the expensive ones even out
+// at the end; split partials grow with it (6 doubles per point and split),
+// which stays far below the time it saves on the 64^3 workload.  A
+// configuration's granularity halves or doubles it.
+long long single_target_wg(int tile_z, int gran) {
+  const long long base = tile_z == 8 ? 32768 : 65536;
+  return gran == 1 ? base / 2 : gran == 2 ? base * 2 : base;
+}
+
+// One problem for a single launch.  The 8x8x8 plan gives its window class
+// and so its size class; the configuration (forced, else tuned, else the
+// defaults; the caller's tile_config wins) then fixes the tile, the split
+// target and the FP32 index mode.  max_splits > 0 caps the split count.
+jefi_status plan_single(const jefi_grid* src, const jefi_history* hist, double dt, int nt, const jefi_grid* obs,
+                        double t, const jefi_fields* out, const jefi_options* opt, const LaunchCfg* force,
+                        long long max_splits, Checked* c) {
+  jefi_status st = check_problem(src, hist, dt, nt, obs, t, out, opt, 0, 8, c);
+  if (st != JEFI_OK) return st;
+  Plan& pl = c->plan;
+  const LaunchCfg cfg =
+      force ? *force
+            : lookup_cfg(size_key(kKeySingle, c->r.precision, window_class(pl), (double)c->no,
+                                  (double)c->no * (double)c->ns));
+  c->cfg = cfg;
+  int tz = choose_tile_z(c->r.tile_config, cfg.tile, (double)c->no);
+  if (pl.multi || pl.wsel > 32) tz = 8;  // those kernels run 8x8x8 tiles only
+  if (pl.empty) return JEFI_OK;
+  if (tz != pl.p.tile_z) set_tiles(pl.p, obs, tz);
+  long long target = single_target_wg(tz, cfg.gran);
+  if (max_splits > 0) target = std::min(target, max_splits * (long long)pl.p.n_tiles);
+  apply_splits(&pl, c->r.precision, target);
+  apply_idx(cfg, c->r, pl.p);
+  return JEFI_OK;
 }
 
 void attach_history(PairParams& p, const jefi_history* hist, int nt) {
@@ -527,11 +617,6 @@ void attach_history(PairParams& p, const jefi_history* hist, int nt) {
   p.ring_bytes_rs = rb < 0x7ffffff0ull ? (unsigned)rb : 0u;
 }
 
-// Workgroups to aim for in a single launch: many waves of them over the
-// 256 CUs, so that the cheap tiles (mostly culled) and the expensive ones
-// even out at the end; split partials grow with it (6 doubles per point and
-// split), which stays far below the time it saves on the 64^3 workload.
-long long single_target_wg(int tile_z) { return tile_z == 8 ? 32768 : 65536; }
 
 // ---- batched evaluation ----------------------------------------------------------
 struct BatchWorkspace {
@@ -542,9 +627,11 @@ struct BatchWorkspace {
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_used[2] = {false, false};
   int turn = 0;
-  // graph per (launch width, cubic stencil, is_f64, index mode, wz), valid for the current `dev` buffer
+  // graph per (launch width, cubic stencil, is_f64, index mode, groups),
+  // valid for the current `dev` buffer
   std::map<long long, hipGraphExec_t> graphs;
   BatchDevice bd{};
+  BatchDevice bdg[2]{};  // the kernel arguments of the two group launches
 };
 std::mutex g_batch_mu;
 std::map<std::pair<int, void*>, BatchWorkspace> g_batch;
@@ -557,7 +644,10 @@ void drop_graphs(BatchWorkspace& w) {
 }
 
 int slots_per_cu(int wz) { return wz == 2 ? 2 : 4; }
-constexpr int kItemsPerSlot = 12;
+// Work items per workgroup slot of a batched launch, by granularity.
+int items_per_slot(int gran) { return gran == 1 ? 6 : gran == 2 ? 24 : 12; }
+// Launch groups of a batch: 8x8x8 tiles (wz 2), then 8x8x4 tiles (wz 1).
+constexpr int kGroupWz[2] = {2, 1};
 
 // Compute units whose workgroup slots a persistent launch fills: all of
 // them less the caller's reserve, which is capped at half the device.
@@ -568,16 +658,26 @@ int launch_cus(int reserve) {
   return cus - std::min(reserve, cus / 2);
 }
 
-jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, int cub, int cus, hipGraphExec_t* out) {
+// Graph of one batched evaluation: queue reset -> threshold tables -> one
+// persistent pair launch per non-empty group -> split reduction.  Its
+// arguments are workspace pointers only (counts live in device memory), so
+// it replays any batch that fits the workspace.
+jefi_status build_graph(BatchWorkspace& w, int is_f64, const bool has[2], int idx, int cub, int cus,
+                        hipGraphExec_t* out) {
   hipGraph_t g;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
-  void* args[] = {&w.bd};
+  for (int q = 0; q < 2; ++q) {
+    w.bdg[q] = w.bd;
+    w.bdg[q].group = q;
+  }
+  void* args0[] = {&w.bdg[0]};
+  void* args1[] = {&w.bdg[1]};
   hipKernelNodeParams kp{};
-  kp.kernelParams = args;
+  kp.kernelParams = args0;
   kp.extra = nullptr;
   kp.sharedMemBytes = 0;
-  hipGraphNode_t n0, n1, n2, n3;
+  hipGraphNode_t n0, n1, prev;
   kp.func = batch_reset_kernel();
   kp.gridDim = dim3(1);
   kp.blockDim = dim3(64);
@@ -588,17 +688,24 @@ jefi_status build_graph(BatchWorkspace& w, int is_f64, int wz, int idx, int cub,
     kp.blockDim = dim3(128);
     e = hipGraphAddKernelNode(&n1, g, &n0, 1, &kp);
   }
-  if (e == hipSuccess) {
-    kp.func = batch_pair_kernel(is_f64, wz, idx, cub);
-    kp.gridDim = dim3(cus * slots_per_cu(wz));
-    kp.blockDim = dim3(batch_pair_threads(wz));
-    e = hipGraphAddKernelNode(&n2, g, &n1, 1, &kp);
+  prev = n1;
+  for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+    if (!has[q]) continue;
+    hipGraphNode_t np;
+    kp.kernelParams = q == 0 ? args0 : args1;
+    kp.func = batch_pair_kernel(is_f64, kGroupWz[q], idx, cub);
+    kp.gridDim = dim3(cus * slots_per_cu(kGroupWz[q]));
+    kp.blockDim = dim3(batch_pair_threads(kGroupWz[q]));
+    e = hipGraphAddKernelNode(&np, g, &prev, 1, &kp);
+    prev = np;
   }
   if (e == hipSuccess) {
+    hipGraphNode_t n3;
+    kp.kernelParams = args0;
     kp.func = batch_epilogue_kernel();
     kp.gridDim = dim3(2048);
     kp.blockDim = dim3(256);
-    e = hipGraphAddKernelNode(&n3, g, &n2, 1, &kp);
+    e = hipGraphAddKernelNode(&n3, g, &prev, 1, &kp);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
@@ -687,18 +794,19 @@ jefi_status jefi_history_push(jefi_history* h, const jefi_grid* src, const void*
   return JEFI_OK;
 }
 
-jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt,
-                             const jefi_grid* obs, double t, const jefi_fields* out,
-                             const jefi_options* opt, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// One field evaluation; force (or NULL) replaces the tuned configuration.
+jefi_status eval_single(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt, const jefi_grid* obs,
+                        double t, const jefi_fields* out, const jefi_options* opt, const LaunchCfg* force,
+                        void* stream) {
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
   if (!out) return fail(JEFI_EINVAL, "output fields are NULL");
   Checked c;
   {
-    // the split count depends on the tile shape: plan once to learn it
-    jefi_status st = check_problem(src, hist, dt, nt, obs, t, out, opt, 0, 0, &c);
-    if (st != JEFI_OK) return st;
-    const int tz = c.plan.p.tile_z;
-    st = check_problem(src, hist, dt, nt, obs, t, out, opt, single_target_wg(tz), tz, &c);
+    jefi_status st = plan_single(src, hist, dt, nt, obs, t, out, opt, force, 0, &c);
     if (st != JEFI_OK) return st;
   }
   if (c.no == 0) return JEFI_OK;
@@ -719,7 +827,7 @@ jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, dou
   jefi_status st = scratch_get(stream, kThrBytes + part_bytes, &scr);
   if (st != JEFI_OK) return st;
   if (!p.direct) p.partial = (double*)((char*)scr->ptr + kThrBytes);
-  if (c.r.precision == JEFI_PREC_F32_COMP && !c.plan.multi) {
+  if (!c.plan.multi) {
     if ((st = prepare_thresholds(p, scr, s)) != JEFI_OK) return st;
   } else {
     p.use_thr = 0;
@@ -734,6 +842,16 @@ jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, dou
   return JEFI_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+jefi_status jefi_eval_fields(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt,
+                             const jefi_grid* obs, double t, const jefi_fields* out,
+                             const jefi_options* opt, void* stream) {
+  return eval_single(src, hist, dt, nt, obs, t, out, opt, nullptr, stream);
+}
+
 jefi_status jefi_eval_fields_noalloc(const jefi_grid* src, const jefi_history* hist, double dt, int32_t nt,
                                      const jefi_grid* obs, double t, const jefi_fields* out,
                                      const jefi_options* opt, void* stream) {
@@ -741,19 +859,17 @@ jefi_status jefi_eval_fields_noalloc(const jefi_grid* src, const jefi_history* h
   if (!out) return fail(JEFI_EINVAL, "output fields are NULL");
   Checked c;
   {
-    jefi_status st = check_problem(src, hist, dt, nt, obs, t, out, opt, 0, 0, &c);
-    if (st != JEFI_OK) return st;
-    const int tz = c.plan.p.tile_z;
     // the split count of jefi_eval_fields, capped so that the FP64 split
     // partials fit the fixed scratch behind the threshold table (one split
     // needs none: the pair kernel then writes E and B itself)
-    long long target = single_target_wg(tz);
-    if (c.no > 0 && c.plan.p.n_tiles > 0) {
+    long long obs_pts = 0;
+    if (!grid_ok(obs, "observation", &obs_pts)) return JEFI_EINVAL;
+    long long max_splits = 0;
+    if (obs_pts > 0) {
       const unsigned long long room = kNoAllocScratchBytes - kThrBytes;
-      const long long fit = (long long)(room / (6ull * sizeof(double) * (unsigned long long)c.no));
-      target = std::min(target, std::max(fit, 1LL) * (long long)c.plan.p.n_tiles);
+      max_splits = std::max(1LL, (long long)(room / (6ull * sizeof(double) * (unsigned long long)obs_pts)));
     }
-    st = check_problem(src, hist, dt, nt, obs, t, out, opt, target, tz, &c);
+    jefi_status st = plan_single(src, hist, dt, nt, obs, t, out, opt, nullptr, max_splits, &c);
     if (st != JEFI_OK) return st;
   }
   if (c.no == 0) return JEFI_OK;
@@ -777,7 +893,7 @@ jefi_status jefi_eval_fields_noalloc(const jefi_grid* src, const jefi_history* h
   hipError_t e = noalloc_scratch(&base);
   if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
   if (!p.direct) p.partial = (double*)((char*)base + kThrBytes);
-  if (c.r.precision == JEFI_PREC_F32_COMP && !c.plan.multi && p.use_thr) {
+  if (!c.plan.multi && p.use_thr) {
     // rebuilt on every call: another call may have left its own table here
     p.thr = (double*)base;
     e = launch_thresholds(p.thr, p.thr_lo, p.thr_n, p.a_f, p.inv_cdt, s);
@@ -831,11 +947,8 @@ jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* his
                                    void* stream) {
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
   Checked c;
-  jefi_status st = check_problem(src, hist, dt, nt, obs, t, nullptr, opt, 0, 0, &c);
+  jefi_status st = plan_single(src, hist, dt, nt, obs, t, nullptr, opt, nullptr, 0, &c);
   if (st != JEFI_OK) return st;
-  const int tz = c.plan.p.tile_z;
-  if ((st = check_problem(src, hist, dt, nt, obs, t, nullptr, opt, single_target_wg(tz), tz, &c)) != JEFI_OK)
-    return st;
   if (!fp && c.no > 0) return fail(JEFI_EINVAL, "fp is NULL");
   if (c.no == 0) return JEFI_OK;
   hipStream_t s = (hipStream_t)stream;
@@ -848,7 +961,7 @@ jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* his
   p.fp = (unsigned long long*)fp;
   Scratch* scr = nullptr;
   if ((st = scratch_get(stream, kThrBytes, &scr)) != JEFI_OK) return st;
-  if (c.r.precision == JEFI_PREC_F32_COMP && !c.plan.multi) {
+  if (!c.plan.multi) {
     if ((st = prepare_thresholds(p, scr, s)) != JEFI_OK) return st;
   } else {
     p.use_thr = 0;
@@ -857,7 +970,13 @@ jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* his
   return e == hipSuccess ? JEFI_OK : hip_fail(e, "fingerprint kernel launch");
 }
 
-jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream) {
+namespace {
+
+// A batched evaluation.  force_tiles (per problem: 1 = 8x8x8, 2 = 8x8x4)
+// and force_batch (index mode and items per slot) replace the tuned table,
+// for the autotuner's trials.
+jefi_status eval_batch_impl(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream,
+                            const std::vector<int>* force_tiles, const LaunchCfg* force_batch) {
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
   if (n < 0 || n > kBatchMaxInst) return fail(JEFI_EINVAL, "batch of %d problems (limit %d)", n, kBatchMaxInst);
   if (n == 0) return JEFI_OK;
@@ -880,12 +999,15 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
   const int is_f64 = r0.precision == JEFI_PREC_F64;
   for (int i = 1; i < n; ++i)
     if (cs[i].r.precision != r0.precision) return fail(JEFI_EINVAL, "mixed precisions in one batch");
-  const int tile_z = choose_tile_z(r0.tile_config, r0.precision, obs_sum / n, pair_sum);
-  const int wz = tile_z == 8 ? 2 : 1;
+  // Tile per problem: forced, else the caller's tile_config, else the tuned
+  // entry of its size class within batches, else one size rule for the
+  // whole batch (on the mean observation grid).
+  const int rule_tile = choose_tile_z(0, 0, obs_sum / n) == 8 ? 1 : 2;
+  const LaunchCfg bcfg = force_batch ? *force_batch : lookup_cfg(size_key(kKeyBatch, r0.precision, 0, n, pair_sum));
 
   // Instances the persistent kernel does not take: empty, all-dead, or
   // windows longer than one staging chunk.  They run on their own launches.
-  std::vector<int> batch_idx;
+  std::vector<int> batch_idx, group_of;
   for (int i = 0; i < n; ++i) {
     const jefi_problem& q = probs[i];
     Checked& c = cs[i];
@@ -901,39 +1023,53 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
       if (st != JEFI_OK) return st;
       continue;
     }
+    int tile = force_tiles ? (*force_tiles)[i] : c.r.tile_config;
+    if (tile == 3) tile = choose_tile_z(3, 0, (double)c.no) == 8 ? 1 : 2;  // each problem by its own size
+    if (tile == 0)
+      tile = lookup_cfg(size_key(kKeyMember, c.r.precision, window_class(c.plan), (double)c.no,
+                                 (double)c.no * (double)c.ns)).tile;
+    if (tile == 0) tile = rule_tile;
+    const int tile_z = tile == 1 ? 8 : 4;
     jefi_status st = make_plan(&q.src, &q.obs, q.nt, q.dt, q.hist.newest, q.hist.t0, q.t, c.r, tile_z, 0, &c.plan);
     if (st != JEFI_OK) return st;
     batch_idx.push_back(i);
+    group_of.push_back(tile_z == 8 ? 0 : 1);
   }
   const int nb = (int)batch_idx.size();
   if (nb == 0) return JEFI_OK;
 
-  // Splits: equal-cost items, about kItemsPerSlot per workgroup slot, so
-  // that the last items to finish leave little of the device idle.
+  // Splits: equal-cost items, about items_per_slot(gran) per workgroup slot
+  // of each group's launch, so that the last items to finish leave little
+  // of the device idle.
   int dev = 0;
   (void)hipGetDevice(&dev);
   // items are sized for the whole device, so that a reserve changes only how
   // many workgroups run at once, not the decomposition (nor the results)
   const int cus = launch_cus(0);
   const int run_cus = launch_cus(cs[0].r.reserve_cus);  // the options are shared
-  const int tile_pts = 64 * (tile_z == 8 ? 8 : 4);
-  double total_cost = 0.0;
+  const int ips = items_per_slot(bcfg.gran);
+  double group_cost[2] = {0.0, 0.0};
   for (int k = 0; k < nb; ++k) {
     const PairParams& p = cs[batch_idx[k]].plan.p;
-    total_cost += (double)p.n_tiles * tile_pts * (double)p.n_bricks * kBrickCells;
+    const int tile_pts = 64 * p.tile_z;
+    group_cost[group_of[k]] += (double)p.n_tiles * tile_pts * (double)p.n_bricks * kBrickCells;
   }
-  const double target = std::max(total_cost / ((double)kItemsPerSlot * cus * slots_per_cu(wz)), 1.0);
-  std::vector<BatchItem> items;
+  double group_target[2];
+  for (int q = 0; q < 2; ++q)
+    group_target[q] = std::max(group_cost[q] / ((double)ips * cus * slots_per_cu(kGroupWz[q])), 1.0);
+  std::vector<BatchItem> gitems[2];
   std::vector<PairParams> params((size_t)nb);
   std::vector<EpilogueParams> epi((size_t)nb);
   std::vector<long long> prefix((size_t)nb + 1, 0);
   size_t part_doubles = 0;
-  const int G = (is_f64 ? 1 : 2) * wz;
   for (int k = 0; k < nb; ++k) {
     const int i = batch_idx[k];
+    const int q = group_of[k];
     PairParams p = cs[i].plan.p;
+    const int tile_pts = 64 * p.tile_z;
+    const int G = (is_f64 ? 1 : 2) * kGroupWz[q];
     const double per_tile = (double)tile_pts * (double)p.n_bricks * kBrickCells;
-    long long splits = (long long)std::ceil(per_tile / target);
+    long long splits = (long long)std::ceil(per_tile / group_target[q]);
     long long max_splits = std::max(1, p.n_bricks / (4 * G));
     splits = std::max(1LL, std::min(splits, max_splits));
     long long bps = (p.n_bricks + splits - 1) / splits;
@@ -946,31 +1082,37 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
     p.B = probs[i].out.B;
     p.out_f64 = probs[i].out.dtype == JEFI_F64;
     p.direct = p.n_splits == 1;
-    if (is_f64) p.use_thr = 0;
     if (!p.direct) part_doubles += (size_t)p.n_splits * 6 * (size_t)cs[i].no;
     params[k] = p;
     const double item_cost = (double)tile_pts * (double)bps * kBrickCells;
-    for (int wg = 0; wg < p.n_wg; ++wg) items.push_back({k, wg, item_cost});
+    for (int wg = 0; wg < p.n_wg; ++wg) gitems[q].push_back({k, wg, item_cost});
   }
-  std::stable_sort(items.begin(), items.end(), [](const BatchItem& a, const BatchItem& b) { return a.cost > b.cost; });
+  for (int q = 0; q < 2; ++q)
+    std::stable_sort(gitems[q].begin(), gitems[q].end(),
+                     [](const BatchItem& a, const BatchItem& b) { return a.cost > b.cost; });
   // One FP32 index mode for the whole launch (both give the same indices):
-  // the threshold table when every instance has one and instances that
-  // prefer it carry at least half of the work.
+  // the tuned one, else the threshold table when every instance has one
+  // and instances that prefer it carry at least half of the work.
   int idx = 0;
   if (!is_f64) {
     bool all_thr = true;
     double want = 0.0, total = 0.0;
     for (int k = 0; k < nb; ++k) {
       const PairParams& p = params[k];
-      const double cost = (double)p.n_tiles * tile_pts * (double)p.n_bricks;
+      const double cost = (double)p.n_tiles * 64 * p.tile_z * (double)p.n_bricks;
       all_thr = all_thr && p.use_thr;
       total += cost;
       if (p.exact_idx) want += cost;
     }
-    idx = all_thr && 2.0 * want >= total ? 1 : 0;
+    const bool forced = (r0.flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE)) != 0;
+    if (!forced && bcfg.idx != 0)
+      idx = bcfg.idx == 2 && all_thr ? 1 : 0;
+    else
+      idx = all_thr && 2.0 * want >= total ? 1 : 0;
   }
-  const int n_items = (int)items.size();
-
+  const int n_items0 = (int)gitems[0].size();
+  const int n_items = n_items0 + (int)gitems[1].size();
+  const bool has[2] = {!gitems[0].empty(), !gitems[1].empty()};
   // Workspace layout (device): params | items | counts | counter | epi | prefix | thresholds | partials
   const size_t o_params = 0;
   const size_t o_items = align_up(o_params + sizeof(PairParams) * nb, 256);
@@ -1047,10 +1189,15 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
   char* hb = (char*)w.host[b];
   std::memcpy(hb + o_params, params.data(), sizeof(PairParams) * nb);
   int2* hi = (int2*)(hb + o_items);
-  for (int q = 0; q < n_items; ++q) hi[q] = make_int2(items[q].inst, items[q].wg);
+  for (int q = 0; q < 2; ++q)
+    for (size_t a = 0; a < gitems[q].size(); ++a)
+      hi[(q ? n_items0 : 0) + a] = make_int2(gitems[q][a].inst, gitems[q][a].wg);
   int* hc = (int*)(hb + o_counts);
-  hc[0] = n_items;
-  hc[1] = nb;
+  hc[0] = nb;
+  hc[1] = n_items0;
+  hc[2] = 0;
+  hc[3] = n_items - n_items0;
+  hc[4] = n_items0;
   std::memcpy(hb + o_epi, epi.data(), sizeof(EpilogueParams) * nb);
   std::memcpy(hb + o_prefix, prefix.data(), sizeof(long long) * (nb + 1));
   if ((e = hipMemcpyAsync(w.dev, hb, host_bytes, hipMemcpyHostToDevice, s)) != hipSuccess)
@@ -1060,6 +1207,7 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
   // Graph of reset -> thresholds -> persistent pairs -> epilogue, pointer
   // arguments only: rebuilt only when the workspace moves.
   BatchDevice bd;
+  std::memset(&bd, 0, sizeof bd);  // compared bytewise below, padding included
   bd.params = (const PairParams*)(dbase + o_params);
   bd.items = (const int2*)(dbase + o_items);
   bd.counts = (const int*)(dbase + o_counts);
@@ -1072,11 +1220,11 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
   }
   // one stencil for the whole batch (the options are shared)
   const int cub = nb > 0 && (params[0].stencil & kStencilCubic) ? 1 : 0;
-  const long long gkey = (long long)run_cus * 32 + cub * 16 + is_f64 * 8 + idx * 4 + wz;
+  const long long gkey = (long long)run_cus * 64 + cub * 16 + is_f64 * 8 + idx * 4 + (has[0] ? 2 : 0) + (has[1] ? 1 : 0);
   auto it = w.graphs.find(gkey);
   if (it == w.graphs.end()) {
     hipGraphExec_t ge;
-    jefi_status st = build_graph(w, is_f64, wz, idx, cub, run_cus, &ge);
+    jefi_status st = build_graph(w, is_f64, has, idx, cub, run_cus, &ge);
     if (st != JEFI_OK) return st;
     it = w.graphs.emplace(gkey, ge).first;
   }
@@ -1084,66 +1232,198 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
   return JEFI_OK;
 }
 
+}  // namespace
+
+jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream) {
+  return eval_batch_impl(probs, n, opt, stream, nullptr, nullptr);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Mean milliseconds per run of `run` over `reps` runs after one warm-up
+// (which also builds graphs), timed with events on the stream.
+template <class F>
+jefi_status time_runs(F run, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, double* ms) {
+  jefi_status st = run();
+  if (st != JEFI_OK) return st;
+  hipError_t e = hipEventRecord(e0, s);
+  if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+  for (int q = 0; q < reps; ++q)
+    if ((st = run()) != JEFI_OK) return st;
+  if ((e = hipEventRecord(e1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+  if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+  float f = 0.f;
+  (void)hipEventElapsedTime(&f, e0, e1);
+  *ms = (double)f / reps;
+  return JEFI_OK;
+}
+
+// A change of configuration is kept only when it is faster by this factor
+// (run-to-run noise of a few tenths of a percent must not flip choices).
+constexpr double kTuneGain = 0.99;
+
+jefi_status tune_single(const jefi_problem& q, const jefi_options& o, int reps, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1, int* best_config, double* best_ms) {
+  Checked c;
+  jefi_status st = plan_single(&q.src, &q.hist, q.dt, q.nt, &q.obs, q.t, &q.out, &o, nullptr, 0, &c);
+  if (st != JEFI_OK) return st;
+  // 8x8x4 tiles only with 32-slot windows; both index modes only where the
+  // FP32 path has a threshold table and the caller's flags leave it open
+  Checked c8;
+  if ((st = check_problem(&q.src, &q.hist, q.dt, q.nt, &q.obs, q.t, &q.out, &o, 0, 8, &c8)) != JEFI_OK) return st;
+  const int wcls = window_class(c8.plan);
+  const int n_tiles = wcls == 0 ? 2 : 1;
+  const bool idx_free = c.r.precision == JEFI_PREC_F32_COMP && c8.plan.p.use_thr &&
+                        !(c.r.flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE));
+  LaunchCfg best{};
+  double best_t = -1.0;
+  for (int tile = 1; tile <= n_tiles; ++tile)
+    for (int idx = idx_free ? 1 : 0; idx <= (idx_free ? 2 : 0); ++idx)
+      for (int gran = 0; gran <= 2; ++gran) {
+        const LaunchCfg cfg{tile, idx, gran};
+        double ms = 0.0;
+        st = time_runs([&]() { return eval_single(&q.src, &q.hist, q.dt, q.nt, &q.obs, q.t, &q.out, &o, &cfg, s); },
+                       reps, s, e0, e1, &ms);
+        if (st != JEFI_OK) return st;
+        if (best_t < 0.0 || ms < best_t) {
+          best = cfg;
+          best_t = ms;
+        }
+      }
+  store_cfgs({{size_key(kKeySingle, c.r.precision, wcls, (double)c.no, (double)c.no * (double)c.ns), best}});
+  *best_config = cfg_pack(best);
+  *best_ms = best_t;
+  return JEFI_OK;
+}
+
+// A batch: greedy coordinate search from the untuned launch.  Each size
+// class of instances (precision, window class, observation points, pairs)
+// tries the other tile; then the batch tries both index modes and the
+// other work granularities.  Kept changes go to the table: member entries
+// per size class, one entry for the batch's class.
+jefi_status tune_batch(const jefi_problem* probs, int n, const jefi_options& o, int reps, hipStream_t s,
+                       hipEvent_t e0, hipEvent_t e1, int* best_config, double* best_ms) {
+  std::vector<Checked> cs((size_t)n);
+  double obs_sum = 0.0, pair_sum = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const jefi_problem& q = probs[i];
+    jefi_status st = check_problem(&q.src, &q.hist, q.dt, q.nt, &q.obs, q.t, &q.out, &o, 0, 8, &cs[i]);
+    if (st != JEFI_OK) return st;
+    obs_sum += (double)cs[i].no;
+    pair_sum += (double)cs[i].no * (double)cs[i].ns;
+  }
+  const Resolved& r0 = cs[0].r;
+  const int rule_tile = choose_tile_z(0, 0, obs_sum / n) == 8 ? 1 : 2;
+  std::vector<int> tiles((size_t)n, rule_tile);
+  // size classes of the instances the persistent launch takes, heaviest first
+  std::map<long long, double> weight;
+  std::vector<long long> key((size_t)n, -1);
+  for (int i = 0; i < n; ++i) {
+    const Checked& c = cs[i];
+    if (c.no == 0 || c.ns == 0 || c.plan.all_dead || c.plan.multi || c.plan.wsel > 32) continue;
+    key[i] = size_key(kKeyMember, c.r.precision, window_class(c.plan), (double)c.no, (double)c.no * (double)c.ns);
+    weight[key[i]] += (double)c.no * (double)c.ns;
+  }
+  std::vector<std::pair<double, long long>> order;
+  for (const auto& kv : weight) order.push_back({kv.second, kv.first});
+  std::sort(order.rbegin(), order.rend());
+  LaunchCfg bc{};
+  auto trial = [&](const std::vector<int>& t, const LaunchCfg& b, double* ms) {
+    return time_runs([&]() { return eval_batch_impl(probs, n, &o, s, &t, &b); }, reps, s, e0, e1, ms);
+  };
+  double best_t = 0.0;
+  jefi_status st = trial(tiles, bc, &best_t);
+  if (st != JEFI_OK) return st;
+  for (const auto& cls : order) {
+    std::vector<int> t2 = tiles;
+    for (int i = 0; i < n; ++i)
+      if (key[i] == cls.second) t2[i] = 3 - t2[i];
+    double ms = 0.0;
+    if ((st = trial(t2, bc, &ms)) != JEFI_OK) return st;
+    if (ms < kTuneGain * best_t) {
+      tiles = t2;
+      best_t = ms;
+    }
+  }
+  const bool idx_free = r0.precision == JEFI_PREC_F32_COMP && !(r0.flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE));
+  if (idx_free) {
+    LaunchCfg keep = bc;
+    for (int idx = 1; idx <= 2; ++idx) {
+      LaunchCfg b2 = bc;
+      b2.idx = idx;
+      double ms = 0.0;
+      if ((st = trial(tiles, b2, &ms)) != JEFI_OK) return st;
+      if (ms < kTuneGain * best_t) {
+        keep = b2;
+        best_t = ms;
+      }
+    }
+    bc = keep;
+  }
+  {
+    LaunchCfg keep = bc;
+    for (int gran = 1; gran <= 2; ++gran) {
+      LaunchCfg b2 = bc;
+      b2.gran = gran;
+      double ms = 0.0;
+      if ((st = trial(tiles, b2, &ms)) != JEFI_OK) return st;
+      if (ms < kTuneGain * best_t) {
+        keep = b2;
+        best_t = ms;
+      }
+    }
+    bc = keep;
+  }
+  std::vector<std::pair<long long, LaunchCfg>> entries;
+  for (const auto& cls : order) {
+    for (int i = 0; i < n; ++i)
+      if (key[i] == cls.second) {
+        entries.push_back({cls.second, LaunchCfg{tiles[i], 0, 0}});
+        break;
+      }
+  }
+  entries.push_back({size_key(kKeyBatch, r0.precision, 0, n, pair_sum), bc});
+  store_cfgs(entries);
+  *best_config = cfg_pack(bc);
+  *best_ms = best_t;
+  return JEFI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 jefi_status jefi_autotune(const jefi_problem* probs, int32_t n, const jefi_options* opt, int32_t reps,
                           void* stream, int32_t* best_config, double* best_ms) {
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
   if (!probs || n < 1) return fail(JEFI_EINVAL, "autotune needs at least one problem");
+  if (n > kBatchMaxInst) return fail(JEFI_EINVAL, "batch of %d problems (limit %d)", n, kBatchMaxInst);
   if (reps < 1) reps = 3;
   jefi_options o;
   if (opt)
     o = *opt;
   else
     jefi_options_default(&o);
-  double obs_sum = 0.0, pair_sum = 0.0;
-  for (int i = 0; i < n; ++i) {
-    long long ns = 0, no = 0;
-    if (!grid_ok(&probs[i].src, "source", &ns) || !grid_ok(&probs[i].obs, "observation", &no)) return JEFI_EINVAL;
-    obs_sum += (double)no;
-    pair_sum += (double)no * (double)ns;
-  }
+  o.tile_config = 0;  // the trials set the tile
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0, e1;
   hipError_t e;
   if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-  if ((e = hipEventCreate(&e1)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-  int best = 0;
-  double best_t = 0.0;
-  jefi_status st = JEFI_OK;
-  for (int cfg = 1; cfg <= 2 && st == JEFI_OK; ++cfg) {
-    o.tile_config = cfg;
-    auto run = [&]() {
-      return n == 1 ? jefi_eval_fields(&probs[0].src, &probs[0].hist, probs[0].dt, probs[0].nt, &probs[0].obs,
-                                       probs[0].t, &probs[0].out, &o, stream)
-                    : jefi_eval_batch(probs, n, &o, stream);
-    };
-    if ((st = run()) != JEFI_OK) break;  // warm-up (also builds graphs)
-    (void)hipEventRecord(e0, s);
-    for (int q = 0; q < reps && st == JEFI_OK; ++q) st = run();
-    (void)hipEventRecord(e1, s);
-    if (st != JEFI_OK) break;
-    if ((e = hipEventSynchronize(e1)) != hipSuccess) {
-      st = hip_fail(e, "hipEventSynchronize");
-      break;
-    }
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    const double per = (double)ms / reps;
-    if (best == 0 || per < best_t) {
-      best = cfg;
-      best_t = per;
-    }
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
   }
+  int best = 0;
+  double ms = 0.0;
+  const jefi_status st = n == 1 ? tune_single(probs[0], o, reps, s, e0, e1, &best, &ms)
+                                : tune_batch(probs, n, o, reps, s, e0, e1, &best, &ms);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != JEFI_OK) return st;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_load_locked();
-    g_tune[tune_key(o.precision, obs_sum / n, pair_sum)] = best;
-    tune_store_locked();
-  }
   if (best_config) *best_config = best;
-  if (best_ms) *best_ms = best_t;
+  if (best_ms) *best_ms = ms;
   return JEFI_OK;
 }
 

@@ -14,8 +14,10 @@ constexpr int kTileEdge = 8;
 constexpr int kThreads = 512;
 // Slice-window slots staged per source cell and launch variant.
 constexpr int kWmax = 32;
-// Largest table of slice-boundary thresholds a launch stages in LDS.
+// Largest table of slice-boundary thresholds a launch stages in LDS
+// (FP32 and FP64 kernels: the FP64 staging planes take twice the LDS).
 constexpr int kThrMax = 1024;
+constexpr int kThrMax64 = 512;
 
 struct GridD {
   int n[3];
@@ -84,13 +86,18 @@ struct EpilogueParams {
 };
 
 // Batched launch: per-instance parameters and work items live in device memory.
+// Instances of a batch fall in up to two launch groups (8x8x8 and 8x8x4
+// observation tiles), each a persistent launch over its own range of the
+// item list with its own queue head.
 struct BatchDevice {
   const PairParams* params;   // [n_inst]
   const int2* items;          // [n_items] (instance, workgroup id within the instance)
-  const int* counts;          // counts[0] = n_items, counts[1] = n_inst
-  int* counter;               // work-queue head
+  const int* counts;          // counts[0] = n_inst; group g: counts[1 + 2g] = its items,
+                              // counts[2 + 2g] = index of its first item
+  int* counter;               // work-queue heads, one per group
   const EpilogueParams* epi;  // [n_inst] (n_splits == 0 for instances written directly)
   const long long* epi_prefix;  // [n_inst + 1] cumulative 6 * n_obs of instances with an epilogue
+  int group;                  // the group a persistent launch serves
 };
 
 struct DumpParams {

@@ -30,6 +30,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <climits>
 #include <map>
 #include <mutex>
 
@@ -422,7 +423,8 @@ __device__ __forceinline__ TileGeom tile_geom(const PP& p, int tile) {
 // must be clamped to the window's slot -2 entry: zero, or the held slice 0
 // with zero derivative), bits 8..15 = valid cells;
 // tf = brick corner relative to
-// the tile reference in FP32, in units of c dt; cc = canonical x0, x1, y0, y1, z0, z1.
+// the tile reference in FP32, in units of c dt, and (bit pattern of tf.w) the
+// brick row by + nby * bz; cc = canonical x0, x1, y0, y1, z0, z1.
 template <class PP>
 __device__ __forceinline__ void brick_info(const PP& p, const TileGeom& g, int b, int b_end,
                                            int4& ti, float4& tf, double cc[6]) {
@@ -473,7 +475,7 @@ __device__ __forceinline__ void brick_info(const PP& p, const TileGeom& g, int b
   const int vmask = (i1 > i0 ? 0xff : 0x55) & (j1 > j0 ? 0xff : 0x33) & (k1 > k0 ? 0xff : 0x0f);
   ti = make_int4(max(jlo, -2), jhi, (dead ? 1 : 0) | (near ? 2 : 0) | (jlo < -2 ? 4 : 0) | (vmask << 8), b);
   tf = make_float4((float)((cc[0] - g.refx) * p.inv_cdt), (float)((cc[2] - g.refy) * p.inv_cdt),
-                   (float)((cc[4] - g.refz) * p.inv_cdt), 0.f);
+                   (float)((cc[4] - g.refz) * p.inv_cdt), __int_as_float(by + p.nby * bz));
 }
 
 template <typename T, int G, bool FP, bool MULTI>
@@ -809,15 +811,30 @@ __device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, fl
   bB[2] = __builtin_fmaf(-Ly, ux, bB[2]);
 }
 
-// Field contribution of one pair from its LDS entry (FP64).
-template <bool CUB>
-__device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, double f, double R, double dx,
-                                            double dy, double dz, double dE[3], double dB[3], double dsc) {
+// 1/R in FP64: hardware reciprocal estimate and two Newton steps.
+__device__ __forceinline__ double recip_f64(double R) {
   double ri = __builtin_amdgcn_rcp(R);
   double er = __builtin_fma(-R, ri, 1.0);
   ri = __builtin_fma(ri, er, ri);
   er = __builtin_fma(-R, ri, 1.0);
-  ri = __builtin_fma(ri, er, ri);
+  return __builtin_fma(ri, er, ri);
+}
+
+// 1/sqrt(r2) in FP64: hardware estimate (about 2^-23 relative) and two
+// Newton steps y += y (1/2 - (r2/2) y^2), each squaring the relative error.
+__device__ __forceinline__ double rsqrt_f64(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  const double hr = 0.5 * r2;
+  double e = __builtin_fma(-hr, y * y, 0.5);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-hr, y * y, 0.5);
+  return __builtin_fma(y, e, y);
+}
+
+// Field contribution of one pair from its LDS entry (FP64); ri = 1/R.
+template <bool CUB>
+__device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, double f, double ri, double dx,
+                                            double dy, double dz, double dE[3], double dB[3], double dsc) {
   double v[4], w[4];
   entry_at<CUB>(lds, PU, e, f, dsc, v, w);
   const double rho = v[0], jx = v[1], jy = v[2], jz = v[3];
@@ -866,7 +883,7 @@ struct FastShape {
   static constexpr int NPL = Traits<T>::kPlanes;
   static constexpr int CS = W + 1;                           // cell stride in entries (one pad entry)
   static constexpr int PU = G * kBrickCells * CS;            // 16-byte units per plane
-  static constexpr int THR = sizeof(T) == 4 ? kThrMax : 1;
+  static constexpr int THR = sizeof(T) == 4 ? kThrMax : kThrMax64;
   static_assert(G >= 1, "window too long for this shape");
 };
 
@@ -896,10 +913,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   const int tile = bid - split * p.n_tiles;
   const TileGeom tg = tile_geom(p, tile);
   const int t = (int)threadIdx.x;
-  if constexpr (sizeof(T) == 4) {
-    if (p.use_thr)
-      for (int i = t; i < p.thr_n; i += kThreads) thr[i] = p.thr[i];
-  }
+  if (p.use_thr)
+    for (int i = t; i < p.thr_n; i += kThreads) thr[i] = p.thr[i];
   const int w = t >> 6, l = t & 63;
   const int ix = tg.ix0 + (w & 1) * 4 + (l & 3);
   const int iy = tg.iy0 + ((w >> 1) & 1) * 4 + ((l >> 2) & 3);
@@ -1071,6 +1086,12 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   // error-free two-sum into the running totals
   float bE[3] = {0.f, 0.f, 0.f}, bB[3] = {0.f, 0.f, 0.f};
   int n_blk = 0;
+  // y and z parts of the full-brick geometry, kept while consecutive bricks
+  // lie in one brick row (the same y and z cells): FP32 separations and
+  // sums of squares, canonical FP64 squares
+  int row_key = -1;
+  float sy0 = 0.f, sy1 = 0.f, sz0 = 0.f, sz1 = 0.f, yzs[4] = {0.f, 0.f, 0.f, 0.f};
+  double ey2s[2] = {0.0, 0.0}, ez2s[2] = {0.0, 0.0};
   for (bool more = b_begin < b_end; more;) {
     write_round(pos, cnt);
     const int npos = pos + cnt;
@@ -1110,17 +1131,36 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         const int mlo = -off;
         const double* bc = tab_c[q];
         const float4 tf = tab_f[q];
-        const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
-        const float d1x = d0x - hsx, d1y = d0y - hsy, d1z = d0z - hsz;
+        const int row = __builtin_amdgcn_readfirstlane(__float_as_int(tf.w));
+        if (row != row_key) {
+          row_key = row;
+          sy0 = yo - tf.y;
+          sz0 = zo - tf.z;
+          sy1 = sy0 - hsy;
+          sz1 = sz0 - hsz;
+          const float y2[2] = {sy0 * sy0, sy1 * sy1};
+          const float z2[2] = {sz0 * sz0, sz1 * sz1};
+          yzs[0] = y2[0] + z2[0];
+          yzs[1] = y2[1] + z2[0];
+          yzs[2] = y2[0] + z2[1];
+          yzs[3] = y2[1] + z2[1];
+          if constexpr (IDX == 1) {
+            const double ey[2] = {roy - bc[2], roy - bc[3]};
+            const double ez[2] = {roz - bc[4], roz - bc[5]};
+            ey2s[0] = ey[0] * ey[0];
+            ey2s[1] = ey[1] * ey[1];
+            ez2s[0] = ez[0] * ez[0];
+            ez2s[1] = ez[1] * ez[1];
+          }
+        }
+        const float d0x = xo - tf.x, d1x = d0x - hsx;
+        const float d0y = sy0, d1y = sy1, d0z = sz0, d1z = sz1;
         const float x2[2] = {d0x * d0x, d1x * d1x};
-        const float y2[2] = {d0y * d0y, d1y * d1y};
-        const float z2[2] = {d0z * d0z, d1z * d1z};
-        const float yz[4] = {y2[0] + z2[0], y2[1] + z2[0], y2[0] + z2[1], y2[1] + z2[1]};
         float ri[8], fr[8], uu[8];
         int m[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-          const float r2 = x2[c & 1] + yz[c >> 1];
+          const float r2 = x2[c & 1] + yzs[c >> 1];
           ri[c] = __builtin_amdgcn_rsqf(r2);
           uu[c] = __builtin_fmaf(-r2, ri[c], af32);
         }
@@ -1134,14 +1174,12 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
 #pragma unroll
           for (int c = 0; c < 8; ++c) tn[c] = thr_at[nn[c]];
           const double ex[2] = {rox - bc[0], rox - bc[1]};
-          const double ey[2] = {roy - bc[2], roy - bc[3]};
-          const double ez[2] = {roz - bc[4], roz - bc[5]};
-          const double ez2[2] = {ez[0] * ez[0], ez[1] * ez[1]};
-          const double exy[4] = {ex[0] * ex[0] + ey[0] * ey[0], ex[1] * ex[1] + ey[0] * ey[0],
-                                 ex[0] * ex[0] + ey[1] * ey[1], ex[1] * ex[1] + ey[1] * ey[1]};
+          const double ex2[2] = {ex[0] * ex[0], ex[1] * ex[1]};
+          // canonical r2 = (dx*dx + dy*dy) + dz*dz
+          const double exy[4] = {ex2[0] + ey2s[0], ex2[1] + ey2s[0], ex2[0] + ey2s[1], ex2[1] + ey2s[1]};
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
-            const int mn = exy[c & 3] + ez2[c >> 2] <= tn[c] ? nn[c] : nn[c] - 1;
+            const int mn = exy[c & 3] + ez2s[c >> 2] <= tn[c] ? nn[c] : nn[c] - 1;
             m[c] = mn;
             fr[c] = uu[c] - (float)mn;
           }
@@ -1263,10 +1301,57 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         }
       }
     } else {
+#pragma unroll 1
       for (int j = 0; j < cnt; ++j) {
         const int q = (pos + j) & (kBrickRing - 1);
+        const int tz = __builtin_amdgcn_readfirstlane(tab_i[q].z);
+        if ((tz & 1) && !(FP && (tz & 2))) continue;  // fingerprint: dead near bricks still count screening
+        if (p.use_thr && (tz & 0xff02) == 0xff00) {
+          // A full far brick: every pair's canonical floor position is N or
+          // N - 1 for N the integer nearest u (u from a refined 1/sqrt, within
+          // 1e-15 of the canonical value), and it is N iff the canonical r2 is
+          // at most the threshold T(N): no correctly rounded square root.
+          const int4 ti = tab_i[q];
+          const int off = p.a_i - ti.x;  // window slot of floor position m: m + off
+          const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
+          // below mlo lies the zero entry of pairs wholly before the oldest
+          // slice (only bricks flagged by bit 2 have such pairs)
+          const int mlo = (tz & 4) ? -off : INT_MIN;
+          const double* bc = tab_c[q];
+          const double ex[2] = {rox - bc[0], rox - bc[1]};
+          const double ey[2] = {roy - bc[2], roy - bc[3]};
+          const double ez[2] = {roz - bc[4], roz - bc[5]};
+          const double x2[2] = {ex[0] * ex[0], ex[1] * ex[1]};
+          const double y2[2] = {ey[0] * ey[0], ey[1] * ey[1]};
+          const double z2[2] = {ez[0] * ez[0], ez[1] * ez[1]};
+          if (!FP && (tz & 4) && !(p.stencil & kStencilHold)) {
+            // straddling the switch-on front: skip the brick for this
+            // wavefront when even its nearest cell lies wholly before slice -1
+            // (FP addition is monotone, so this is the smallest pair r2)
+            const double r2min = (__builtin_fmin(x2[0], x2[1]) + __builtin_fmin(y2[0], y2[1])) +
+                                 __builtin_fmin(z2[0], z2[1]);
+            if (!__any(r2min <= thr_at[max(-1 - p.a_i, p.thr_lo)])) continue;
+          }
+          const double exy[4] = {x2[0] + y2[0], x2[1] + y2[0], x2[0] + y2[1], x2[1] + y2[1]};
+          const int s_base = FP ? brick_s_base(ti.w) : 0;
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const double r2 = exy[c & 3] + z2[c >> 2];  // (dx*dx + dy*dy) + dz*dz
+            const double ri = rsqrt_f64(r2);
+            const double u = __builtin_fma(-(r2 * ri), p.inv_cdt, p.a_f);
+            const int nn = (int)__builtin_rint(u);
+            const int mm = r2 <= thr_at[nn] ? nn : nn - 1;
+            if (FP) {
+              fpa.add(p.a_i + mm, cell_s(s_base, c));
+              continue;
+            }
+            const int e = cellbase + c * kCellStride + max(mm, mlo);
+            pair_fields<CUB>(lds, PU, e, u - (double)mm, ri, ex[c & 1], ey[(c >> 1) & 1], ez[c >> 2], dE, dB,
+                             inv_dt);
+          }
+          continue;
+        }
         const int4 ti = tab_i[q];
-        if ((ti.z & 1) && !(FP && (ti.z & 2))) continue;  // fingerprint: dead near bricks still count screening
         const int lo = ti.x;
         const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;
@@ -1304,7 +1389,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
             continue;
           }
           const int e = cellbase + c * kCellStride + min(max(mm, mlo), mhi);
-          pair_fields<CUB>(lds, PU, e, u - fl, R, dx[cx], dy[cy], dz[cz], dE, dB, inv_dt);
+          pair_fields<CUB>(lds, PU, e, u - fl, recip_f64(R), dx[cx], dy[cy], dz[cz], dE, dB, inv_dt);
         }
       }
     }
@@ -1386,14 +1471,15 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ double thr[S::THR];
   __shared__ int qs[2];
   __shared__ int cur;
-  const int n_items = bd.counts[0];
+  const int n_items = bd.counts[1 + 2 * bd.group];
+  const int2* items = bd.items + bd.counts[2 + 2 * bd.group];
   for (;;) {
     __syncthreads();  // the previous item is done with LDS and `cur`
-    if (threadIdx.x == 0) cur = atomicAdd(bd.counter, 1);
+    if (threadIdx.x == 0) cur = atomicAdd(bd.counter + bd.group, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(cur);
     if (it >= n_items) break;
-    const int2 item = bd.items[it];
+    const int2 item = items[it];
     const int inst = __builtin_amdgcn_readfirstlane(item.x);
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
     using CP = const __attribute__((address_space(4))) PairParams;
@@ -1408,7 +1494,7 @@ __global__ void threshold_kernel(double* out, int lo, int n, double af, double i
 }
 
 __global__ void batch_threshold(BatchDevice bd) {
-  const int n_inst = bd.counts[1];
+  const int n_inst = bd.counts[0];
   for (int inst = (int)blockIdx.y; inst < n_inst; inst += (int)gridDim.y) {
     const PairParams& p = bd.params[inst];
     if (!p.use_thr) continue;
@@ -1418,12 +1504,12 @@ __global__ void batch_threshold(BatchDevice bd) {
 }
 
 __global__ void batch_reset(BatchDevice bd) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *bd.counter = 0;
+  if (threadIdx.x < 2 && blockIdx.x == 0) bd.counter[threadIdx.x] = 0;
 }
 
 // Fixed-order split reduction for every instance of a batch that has splits.
 __global__ void batch_epilogue(BatchDevice bd) {
-  const int n_inst = bd.counts[1];
+  const int n_inst = bd.counts[0];
   const long long total = bd.epi_prefix[n_inst];
   for (long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (long long)gridDim.x * blockDim.x) {
@@ -1779,6 +1865,5 @@ hipError_t noalloc_scratch(void** out) {
   *out = it->second;
   return hipSuccess;
 }
-
 
 }  // namespace jefi

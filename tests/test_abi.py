@@ -97,7 +97,7 @@ def test_eval_validation(case):
     elif case == "both-flags":
         opt.flags = J.JEFI_FLAG_INDEX_GUARD | J.JEFI_FLAG_INDEX_TABLE | J.JEFI_FLAG_PAST_HOLD
     elif case == "bad-tile":
-        opt.tile_config = 3
+        opt.tile_config = 4
     elif case == "bad-reserve":
         opt.reserve_cus = -1
     st = J.lib.jefi_eval_fields(src_p, C.byref(h), dt, nt, C.byref(obs), t, C.byref(fields),

@@ -2,7 +2,8 @@
 the same fields as its own single launch (and as the oracle on sampled
 points), for both launch shapes and both precisions; graph replays agree;
 instances the persistent kernel leaves out (empty, wholly-past, long
-windows) still come out right; the autotuner picks a valid shape."""
+windows) still come out right; a batch split into two launch groups (one
+per tile shape) and the autotuner's choices give the same fields."""
 import numpy as np
 import pytest
 
@@ -141,13 +142,75 @@ def test_batch_with_fallback_instances():
         _check_against([batch[k]], [(Er, Br)], TOL["f32"], p.name)
 
 
-def test_autotune_picks_a_shape(tmp_path, monkeypatch):
+def _mixed_batch(seed=41):
+    """Small instances and two with at least 32768 observation points (a
+    32^3 grid of the source spacing around an 8^3 or 12^3 source), so that
+    the per-problem size rule puts them in different launch groups."""
+    probs = _small_batch(6, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    for i, es in enumerate((8, 12)):
+        dx = 1.6 / es
+        dt = dx / 2.0
+        nt = 2 * es + 8
+        src = centred_grid((es, es, es), dx)
+        obs = Grid((32, 32, 32), tuple(src.origin[a] - 12 * dx for a in range(3)), (dx, dx, dx))
+        blobs = workloads.draw_blobs(rng, 4, (-0.8, 0.8))
+        probs.append(Problem(f"big{i}", src, obs, blob_history(src, blobs, nt, dt), dt, (nt - 1) * dt, 0.0,
+                             nt - 1, 1.0, workloads.default_screen(src)))
+    return probs
+
+
+def _against_oracle(batch, probs, prec, label, seed=9):
+    rng = np.random.default_rng(seed)
+    for k, p in enumerate(probs):
+        sel = np.sort(rng.choice(p.obs.size, size=min(24, p.obs.size), replace=False))
+        Er, Br = oracle.eval_problem(p, sel=sel)
+        _check_against([(batch[k][0][:, sel], batch[k][1][:, sel])], [(Er, Br)], TOL[prec], f"{label} #{k}")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_mixed_tile_groups(prec):
+    """tile_config 3 (size rule per problem): the large instances run with
+    8x8x8 tiles and the small ones with 8x8x4, as two persistent launches of
+    one batch; every instance matches its own single launch and the oracle."""
     G = _gpu()
-    probs = _small_batch(6, seed=12)
+    probs = _mixed_batch()
+    run = G.BatchRun(probs, prec)
+    batch = run.run_batch(3)
+    solo = run.run_solo(3)
+    _check_against(batch, solo, SOLO[prec], f"mixed groups vs solo {prec}")
+    _against_oracle(batch, probs, prec, f"mixed groups vs oracle {prec}")
+    # and the same problems with one tile for all give the same fields
+    one = run.run_batch(1)
+    _check_against(batch, one, SOLO[prec], f"mixed groups vs one group {prec}")
+
+
+def test_autotune_single_problem():
+    """One problem: every configuration it admits is timed; the packed
+    result is a valid configuration, and tile_config = 0 then evaluates
+    with it and matches the oracle."""
+    G = _gpu()
+    probs = _mixed_batch(seed=5)[-1:]
     run = G.BatchRun(probs, "f32")
-    best, ms = run.J.jefi_autotune(run.problem_structs(), run.options(0), reps=2)
-    assert best in (1, 2) and ms > 0.0
-    # the tuned choice now drives tile_config = 0 and still gives correct fields
+    best, ms = run.J.jefi_autotune(run.problem_structs(), run.options(0), reps=1)
+    tile, idx, gran = best & 3, (best >> 2) & 3, (best >> 4) & 3
+    assert tile in (1, 2) and idx in (1, 2) and gran in (0, 1, 2) and ms > 0.0, best
+    tuned = run.run_solo(0)
+    _against_oracle(tuned, probs, "f32", "tuned single")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_autotune_batch_equals_solo_and_oracle(prec):
+    """A batch: the tuner's greedy search (tile per size class, index mode,
+    granularity) leaves a table under which the batch (tile_config = 0)
+    equals each problem's single launch and the oracle."""
+    G = _gpu()
+    probs = _mixed_batch(seed=13)
+    run = G.BatchRun(probs, prec)
+    best, ms = run.J.jefi_autotune(run.problem_structs(), run.options(0), reps=1)
+    assert best & 3 == 0 and ((best >> 2) & 3) in (0, 1, 2) and ((best >> 4) & 3) in (0, 1, 2), best
+    assert ms > 0.0
     batch = run.run_batch(0)
-    solo = run.run_solo(best)
-    _check_against(batch, solo, SOLO["f32"], "tuned")
+    solo = run.run_solo(0)
+    _check_against(batch, solo, SOLO[prec], f"tuned batch vs solo {prec}")
+    _against_oracle(batch, probs, prec, f"tuned batch vs oracle {prec}")
