@@ -287,7 +287,7 @@ def run_batch_workload(args):
     }
 
 
-def serve_measure(seconds, inflight, reserve_cus, small_arena_bytes=1 << 30):
+def serve_measure(seconds, inflight, reserve_cus, small_arena_bytes=1 << 30, express_pairs=0, express_cus=16):
     """Poisson request stream over 128 sessions through the serving loop:
     real-time replay for latency, back to back for throughput, back to back
     again in a small arena that cannot hold every session (admission by
@@ -331,10 +331,11 @@ def serve_measure(seconds, inflight, reserve_cus, small_arena_bytes=1 << 30):
     free = torch.cuda.mem_get_info()[0]
     arena_bytes = int(min(200e9, 0.6 * free))
 
-    def serve(paced, arena_size):
+    def serve(paced, arena_size, express=True):
         arena = torch.empty(arena_size, dtype=torch.uint8, device="cuda")
         sv = J.Server(arena, precision=J.JEFI_PREC_F32_COMP, max_inflight=inflight, max_batch=256,
-                      reserve_cus=reserve_cus)
+                      reserve_cus=reserve_cus, express_pairs=int(express_pairs) if express else 0,
+                      express_cus=express_cus)
         for sp in specs:
             sv.open_session(sp["session"], grids[sp["session"]], sp["capacity"], sp["capacity"], 0.0, sp["dt"],
                             hist0[sp["session"]].astype(np.float32))
@@ -403,6 +404,10 @@ def serve_measure(seconds, inflight, reserve_cus, small_arena_bytes=1 << 30):
                                                       for d in by_size))
     wall_o, lat_o, bsz_o, outs_o, stats_o = serve(False, arena_bytes)
     log(f"back-to-back: {len(reqs)/wall_o:.1f} req/s")
+    if express_pairs > 0:
+        # the same stream without the express lane: what the lane costs in throughput
+        wall_n, lat_n, bsz_n, outs_n, stats_n = serve(False, arena_bytes, express=False)
+        log(f"back-to-back without the express lane: {len(reqs)/wall_n:.1f} req/s")
     wall_s, lat_s, bsz_s, outs_s, stats_s = serve(False, small_arena_bytes)
     log(f"back-to-back, {small_arena_bytes/2**30:.1f} GiB arena: {len(reqs)/wall_s:.1f} req/s, "
         f"{stats_s['evictions']} evictions, {stats_s['rematerialisations']} re-materialisations")
@@ -477,6 +482,13 @@ def serve_measure(seconds, inflight, reserve_cus, small_arena_bytes=1 << 30):
                     f"{arena_bytes/1e9:.0f} GB (a second back-to-back run in {small_arena_bytes/2**30:.0f} GiB)",
         "requests": len(reqs), "pairs": total_pairs, "session_rings_gb": round(ring_bytes / 1e9, 3),
         "batches_in_flight": inflight, "reserve_cus": reserve_cus,
+        "express_lane": ({"max_pairs": express_pairs, "cus": stats_p["express_cus"],
+                          "cu_masked_streams": bool(stats_p["cu_masked"]),
+                          "paced_express_batches": stats_p["express_batches"],
+                          "back_to_back_without_it": {"req_per_s": round(len(reqs) / wall_n, 2),
+                                                      "value": round(total_pairs / wall_n / 1e9, 3)},
+                          "back_to_back_with_over_without": round(wall_n / wall_o, 3)}
+                         if express_pairs > 0 else None),
         "paced": {"req_per_s": round(len(reqs) / wall_p, 2), "latency_ms": lat_summary(lat_p),
                   "mean_batch": round(float(bsz_p.mean()), 2), "batches": stats_p["batches"],
                   "latency_ms_by_size_quartile": by_size},
@@ -503,7 +515,7 @@ def serve_measure(seconds, inflight, reserve_cus, small_arena_bytes=1 << 30):
 
 def run_serve_workload(args):
     sv = serve_measure(args.serve_seconds, args.serve_inflight, args.serve_reserve_cus,
-                       int(args.serve_small_arena_gib * 2**30))
+                       int(args.serve_small_arena_gib * 2**30), args.serve_express_pairs, args.serve_express_cus)
     b2b = sv["back_to_back"]
     return {
         "metric": METRIC, "value": b2b["value"], "unit": "G pairs/s", "n_gpus": 1,
@@ -828,6 +840,10 @@ def main():
                     help="serve workload: compute units each batch launch leaves free for the others")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson request stream (serving block and --workload serve)")
+    ap.add_argument("--serve-express-pairs", type=float, default=5e7,
+                    help="serving: requests of at most this many pairs take the express lane (0 = none)")
+    ap.add_argument("--serve-express-cus", type=int, default=16,
+                    help="serving: compute units of the express lane")
     ap.add_argument("--serve-small-arena-gib", type=float, default=1.0,
                     help="arena of the serving run whose budget binds (sessions are evicted)")
     ap.add_argument("--no-batch", action="store_true",
@@ -939,7 +955,8 @@ def main():
         res["batch"] = batch_measure(args.batch_steps, 2, tune=not args.no_tune)
     if args.workload == "large" and not args.no_serve:
         res["serve"] = serve_measure(args.serve_seconds, args.serve_inflight, args.serve_reserve_cus,
-                                     int(args.serve_small_arena_gib * 2**30))
+                                     int(args.serve_small_arena_gib * 2**30), args.serve_express_pairs,
+                                     args.serve_express_cus)
         res["p99_latency_ms"] = res["serve"]["paced"]["latency_ms"]["p99"]
 
     if not args.no_parity or not args.no_cpu_baseline:

@@ -299,6 +299,15 @@ typedef struct {
   int32_t reserve_cus;      /* jefi_options.reserve_cus of every batch: with max_inflight >= 3,
                                small requests then start beside large ones instead of waiting
                                for them (lower tail latency, some throughput); 0 = none */
+  int32_t express_cus;      /* compute units of the express lane (0 = 16; at most half the
+                               device; 0 .. 1024, else EINVAL) */
+  uint64_t express_pairs;   /* 0 = no express lane.  Else requests of at most this many pairs
+                               (n_src * n_obs) run in an express lane: one more stream whose
+                               batches use express_cus compute units that the other batches
+                               (max_inflight streams) leave free, through CU-masked streams
+                               where the runtime allows, else through launch sizes; a small
+                               request then never waits behind a persistent launch that holds
+                               the device.  Each session's requests still run in order. */
 } jefi_server_config;
 
 typedef struct {
@@ -326,6 +335,9 @@ typedef struct {
   uint64_t rematerialisations; /* rings brought back from their host shadow after an eviction */
   uint64_t arena_bytes, arena_used, arena_high_water;
   uint64_t pairs;
+  uint64_t express_batches;  /* batches run in the express lane */
+  uint64_t express_cus;      /* its compute units (0 without one) */
+  uint64_t cu_masked;        /* 1 when the lanes run on CU-masked streams */
 } jefi_server_stats;
 
 /* Start a server on the current device.  EINVAL on a bad config, ENOMEM

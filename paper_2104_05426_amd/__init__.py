@@ -70,7 +70,8 @@ class jefi_problem(C.Structure):
 class jefi_server_config(C.Structure):
     _fields_ = [("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("pinned_bytes", C.c_uint64),
                 ("precision", C.c_int32), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
-                ("max_queue", C.c_int32), ("flags", C.c_uint32), ("reserve_cus", C.c_int32)]
+                ("max_queue", C.c_int32), ("flags", C.c_uint32), ("reserve_cus", C.c_int32),
+                ("express_cus", C.c_int32), ("express_pairs", C.c_uint64)]
 
 
 class jefi_request(C.Structure):
@@ -87,7 +88,8 @@ class jefi_result(C.Structure):
 class jefi_server_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("submitted", "completed", "failed", "batches", "max_batch",
                                          "evictions", "rematerialisations", "arena_bytes", "arena_used",
-                                         "arena_high_water", "pairs")]
+                                         "arena_high_water", "pairs", "express_batches", "express_cus",
+                                         "cu_masked")]
 
 
 def _load():
@@ -312,11 +314,11 @@ class Server:
     ``arena``: a device tensor whose bytes the server may use."""
 
     def __init__(self, arena, precision=JEFI_PREC_F32_COMP, max_inflight=2, max_batch=256,
-                 max_queue=65536, pinned_bytes=0, flags=0, reserve_cus=0):
+                 max_queue=65536, pinned_bytes=0, flags=0, reserve_cus=0, express_pairs=0, express_cus=0):
         self.arena = arena
         cfg = jefi_server_config(_ptr(arena), arena.numel() * arena.element_size(), int(pinned_bytes),
                                  int(precision), int(max_inflight), int(max_batch), int(max_queue),
-                                 int(flags), int(reserve_cus))
+                                 int(flags), int(reserve_cus), int(express_cus), int(express_pairs))
         h = C.c_void_p()
         _check(lib.jefi_server_create(C.byref(cfg), C.byref(h)))
         self.h = h

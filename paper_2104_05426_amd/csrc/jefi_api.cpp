@@ -2,6 +2,7 @@
 // planning, per-stream scratch, batched evaluation with a graph-replayed
 // persistent launch, and the launch-shape autotuner.  Device work is in
 // jefi_kernels.hip.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -970,13 +971,16 @@ jefi_status jefi_slice_fingerprint(const jefi_grid* src, const jefi_history* his
   return e == hipSuccess ? JEFI_OK : hip_fail(e, "fingerprint kernel launch");
 }
 
+}  // extern "C"
+
 namespace {
 
 // A batched evaluation.  force_tiles (per problem: 1 = 8x8x8, 2 = 8x8x4)
 // and force_batch (index mode and items per slot) replace the tuned table,
-// for the autotuner's trials.
+// for the autotuner's trials; grid_cus > 0 sizes the persistent launches
+// for that many compute units.
 jefi_status eval_batch_impl(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream,
-                            const std::vector<int>* force_tiles, const LaunchCfg* force_batch) {
+                            const std::vector<int>* force_tiles, const LaunchCfg* force_batch, int grid_cus = 0) {
   if (g_device_failed.load()) return fail(JEFI_EDEVICE, "an earlier HIP failure is sticky");
   if (n < 0 || n > kBatchMaxInst) return fail(JEFI_EINVAL, "batch of %d problems (limit %d)", n, kBatchMaxInst);
   if (n == 0) return JEFI_OK;
@@ -1046,7 +1050,8 @@ jefi_status eval_batch_impl(const jefi_problem* probs, int32_t n, const jefi_opt
   // items are sized for the whole device, so that a reserve changes only how
   // many workgroups run at once, not the decomposition (nor the results)
   const int cus = launch_cus(0);
-  const int run_cus = launch_cus(cs[0].r.reserve_cus);  // the options are shared
+  // the options are shared; a caller's explicit grid wins over its reserve
+  const int run_cus = grid_cus > 0 ? std::min(grid_cus, cus) : launch_cus(cs[0].r.reserve_cus);
   const int ips = items_per_slot(bcfg.gran);
   double group_cost[2] = {0.0, 0.0};
   for (int k = 0; k < nb; ++k) {
@@ -1233,6 +1238,32 @@ jefi_status eval_batch_impl(const jefi_problem* probs, int32_t n, const jefi_opt
 }
 
 }  // namespace
+
+namespace jefi {
+
+int device_cus() { return launch_cus(0); }
+
+bool create_stream_on_cus(hipStream_t* s, int first_cu, int n_cus) {
+  const int cus = launch_cus(0);
+  if (first_cu < 0 || n_cus < 1 || first_cu + n_cus > cus) return false;
+  std::vector<uint32_t> mask((size_t)(cus + 31) / 32, 0u);
+  for (int c = first_cu; c < first_cu + n_cus; ++c) mask[(size_t)c / 32] |= 1u << (c % 32);
+  const hipError_t e = hipExtStreamCreateWithCUMask(s, (uint32_t)mask.size(), mask.data());
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+jefi_status eval_batch_on_cus(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream,
+                              int grid_cus) {
+  return eval_batch_impl(probs, n, opt, stream, nullptr, nullptr, grid_cus);
+}
+
+}  // namespace jefi
+
+extern "C" {
 
 jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream) {
   return eval_batch_impl(probs, n, opt, stream, nullptr, nullptr);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/libjefi.h"
+
 namespace jefi {
 
 // Source bricks: 2x2x2 cells, the unit of the ring layout and of staging.
@@ -135,6 +137,18 @@ int batch_pair_threads(int wz);
 hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);
 hipError_t launch_fill_zero_fields(void* E, void* B, long long n_obs, int out_f64, hipStream_t s);
 hipError_t launch_dump(const DumpParams& p, hipStream_t s);
+
+// Compute units of the current device.
+int device_cus();
+// A non-blocking stream whose kernels run only on compute units
+// first_cu .. first_cu + n_cus - 1 (a CU mask); false if the device or
+// runtime refuses the mask (no stream is created then).
+bool create_stream_on_cus(hipStream_t* s, int first_cu, int n_cus);
+// jefi_eval_batch whose persistent launches fill the workgroup slots of
+// grid_cus compute units (any count from 1 to the device's), for callers
+// that run the batch on a stream restricted to that many units.
+jefi_status eval_batch_on_cus(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream,
+                              int grid_cus);
 
 // Fixed device scratch of the allocation-free evaluation (per GPU): the
 // threshold table and FP64 split partials.

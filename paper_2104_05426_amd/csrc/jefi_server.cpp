@@ -3,7 +3,10 @@
 // of idle sessions (a host shadow of each ring re-materialises them), and
 // continuous batching: a scheduler thread turns admitted requests into
 // batched evaluations on several streams, so requests arriving while others
-// run are launched as soon as a stream slot and memory are free.
+// run are launched as soon as a stream slot and memory are free.  Small
+// requests may take an express lane: one more stream whose batches run on a
+// few compute units that the other batches leave free, so that they never
+// wait behind a persistent launch holding the whole device.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
@@ -102,7 +105,14 @@ struct jefi_server {
   Arena darena;
   char* pbase = nullptr;
   Arena parena;
+  // streams: regular lane [0, n_regular); express lane streams[express];
+  // with CU masks, [express + 1, express + 1 + n_regular): regular streams
+  // on every compute unit, used while a backlog has switched the lane off
   std::vector<hipStream_t> streams;
+  int n_regular = 0;
+  int express = -1;      // stream index of the express lane, -1 without one
+  int express_cus = 0;   // compute units its batches run on
+  bool cu_masked = false;  // lane streams restricted to their compute units
   std::vector<hipEvent_t> events;
   std::mutex mu;
   std::condition_variable cv, done_cv;
@@ -244,29 +254,70 @@ void complete_batch(jefi_server* sv, Batch& b, jefi_status st) {
   sv->events.push_back(b.done);
 }
 
-// Choose the next batch: FIFO over the queue, one request per session, every
-// resource reserved up front; a request that does not fit yet stops the
-// scan (admission in arrival order).
-void admit_and_launch(jefi_server* sv) {
+bool small_request(const jefi_server* sv, const Req& r) {
+  return sv->express >= 0 && r.pairs <= sv->cfg.express_pairs;
+}
+
+// Choose the next batch of one lane: FIFO over the queue, one request per
+// session, every resource reserved up front; a request that does not fit yet
+// stops the scan (admission in arrival order).  With an express lane, it
+// takes only requests of at most express_pairs pairs and the regular lane
+// the others.  A session whose earlier request is left for the other lane
+// is passed over, so each session's requests still run in order.  While
+// more requests wait than one batch holds (a backlog, where latency is the
+// queue's anyway), the express lane admits nothing and the regular lane
+// takes every request, on streams that use every compute unit.
+void admit_and_launch(jefi_server* sv, bool express_lane) {
   if (sv->queue.empty()) return;
-  // a stream with no batch in flight, so that this batch overlaps the others
+  const bool backlog = sv->queue.size() > (size_t)sv->cfg.max_batch;
+  const bool lanes = sv->express >= 0 && !backlog;
+  if (express_lane && !lanes) return;
+  // a stream of this lane with no batch in flight, so that this batch
+  // overlaps the others; at most n_regular regular batches at once
   int si = -1;
-  for (int i = 0; i < (int)sv->streams.size() && si < 0; ++i) {
+  if (express_lane) {
     bool used = false;
-    for (const Batch& f : sv->inflight) used = used || f.stream == i;
-    if (!used) si = i;
+    for (const Batch& f : sv->inflight) used = used || f.stream == sv->express;
+    if (!used) si = sv->express;
+  } else {
+    int regular_inflight = 0;
+    for (const Batch& f : sv->inflight) regular_inflight += f.stream != sv->express;
+    if (regular_inflight >= sv->n_regular) return;
+    const bool full = backlog && sv->cu_masked;
+    const int first = full ? sv->express + 1 : 0;
+    for (int i = first; i < first + sv->n_regular && si < 0; ++i) {
+      bool used = false;
+      for (const Batch& f : sv->inflight) used = used || f.stream == i;
+      if (!used) si = i;
+    }
   }
   if (si < 0) return;
   hipStream_t st = sv->streams[si];
   Batch b;
   b.stream = si;
-  std::unordered_set<uint64_t> in_batch;
+  std::unordered_set<uint64_t> in_batch, passed;
   std::vector<uint64_t> chosen;
   std::vector<hipEvent_t> deps;
   const size_t el = elem_size(sv->cfg.precision);
+  // An express batch stays short (at most four express-sized requests of
+  // work): a later request of one of its sessions in the regular lane waits
+  // for it, and so would that request's whole batch.
+  const uint64_t express_budget = 4 * sv->cfg.express_pairs;
+  uint64_t batch_pairs = 0;
   for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)chosen.size() < sv->cfg.max_batch;) {
     Req& r = sv->reqs[*it];
     Session& s = sv->sessions[r.session];
+    if (express_lane && !chosen.empty() && batch_pairs + r.pairs > express_budget) break;
+    if (passed.count(s.id)) {  // an earlier request of the session is the other lane's
+      ++it;
+      continue;
+    }
+    const bool small = small_request(sv, r);
+    if (lanes && small != express_lane) {
+      passed.insert(s.id);
+      ++it;
+      continue;
+    }
     if (in_batch.count(s.id)) {  // one request per session and batch
       ++it;
       continue;
@@ -336,6 +387,7 @@ void admit_and_launch(jefi_server* sv) {
     r.state = kRunning;
     s.queued--;
     s.busy++;
+    batch_pairs += r.pairs;
     chosen.push_back(*it);
     it = sv->queue.erase(it);
   }
@@ -408,8 +460,15 @@ void admit_and_launch(jefi_server* sv) {
     jefi_options_default(&opt);
     opt.precision = sv->cfg.precision;
     opt.flags = sv->cfg.flags;
-    opt.reserve_cus = sv->cfg.reserve_cus;
-    rc = jefi_eval_batch(probs.data(), (int32_t)probs.size(), &opt, st);
+    if (express_lane) {
+      rc = jefi::eval_batch_on_cus(probs.data(), (int32_t)probs.size(), &opt, st, sv->express_cus);
+    } else {
+      // regular batches on the lane's masked streams leave the express
+      // lane's compute units free
+      const bool beside_express = sv->express >= 0 && si < sv->express;
+      opt.reserve_cus = std::max(sv->cfg.reserve_cus, beside_express ? sv->express_cus : 0);
+      rc = jefi_eval_batch(probs.data(), (int32_t)probs.size(), &opt, st);
+    }
     if (rc == JEFI_EDEVICE) set_sticky(sv, hipErrorUnknown, jefi_last_error());
   }
   if (rc == JEFI_OK) {
@@ -446,6 +505,7 @@ void admit_and_launch(jefi_server* sv) {
   if (e != hipSuccess) set_sticky(sv, e, "hipEventRecord");
   for (uint64_t tk : chosen) sv->sessions[sv->reqs[tk].session].last_done = b.done;
   sv->stats.batches++;
+  if (express_lane) sv->stats.express_batches++;
   if ((uint64_t)chosen.size() > sv->stats.max_batch) sv->stats.max_batch = chosen.size();
   sv->inflight.push_back(std::move(b));
 }
@@ -467,9 +527,10 @@ void scheduler(jefi_server* sv) {
       progress = true;
     }
     if (progress) sv->done_cv.notify_all();
-    if ((int)sv->inflight.size() < sv->cfg.max_inflight && !sv->queue.empty()) {
+    if (!sv->queue.empty()) {
       const size_t before = sv->queue.size();
-      admit_and_launch(sv);
+      admit_and_launch(sv, true);
+      admit_and_launch(sv, false);
       if (sv->queue.size() != before) progress = true;
       sv->done_cv.notify_all();
     }
@@ -493,6 +554,7 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
   if ((cfg->flags & ~known) != 0 || (cfg->flags & both) == both || (cfg->flags & slope_cubic) == slope_cubic)
     return JEFI_EINVAL;
   if (cfg->reserve_cus < 0 || cfg->reserve_cus > 1024) return JEFI_EINVAL;
+  if (cfg->express_cus < 0 || cfg->express_cus > 1024) return JEFI_EINVAL;
   jefi_server* sv = new jefi_server();
   sv->cfg = *cfg;
   if (sv->cfg.max_inflight < 1) sv->cfg.max_inflight = 2;
@@ -509,7 +571,34 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
     return JEFI_ENOMEM;
   }
   sv->parena.reset(sv->cfg.pinned_bytes);
-  for (int i = 0; i < sv->cfg.max_inflight; ++i) {
+  sv->n_regular = sv->cfg.max_inflight;
+  int n_streams = sv->n_regular + (sv->cfg.express_pairs > 0 ? 1 : 0);
+  if (sv->cfg.express_pairs > 0) {
+    // the express lane: the last express_cus compute units (16 by default,
+    // at most half the device); the regular streams take the others
+    const int cus = jefi::device_cus();
+    sv->express_cus = std::max(1, std::min(sv->cfg.express_cus > 0 ? sv->cfg.express_cus : 16, cus / 2));
+    sv->express = sv->n_regular;
+    sv->cu_masked = true;
+    for (int i = 0; i < n_streams && sv->cu_masked; ++i) {
+      hipStream_t s;
+      const bool ok = i == sv->express ? jefi::create_stream_on_cus(&s, cus - sv->express_cus, sv->express_cus)
+                                       : jefi::create_stream_on_cus(&s, 0, cus - sv->express_cus);
+      if (ok)
+        sv->streams.push_back(s);
+      else
+        sv->cu_masked = false;
+    }
+    if (!sv->cu_masked) {
+      // the runtime refused the masks: plain streams, and the lanes kept apart
+      // by launch sizes alone (regular launches leave the units free)
+      for (hipStream_t x : sv->streams) (void)hipStreamDestroy(x);
+      sv->streams.clear();
+    } else {
+      n_streams += sv->n_regular;  // unmasked regular streams for backlogs
+    }
+  }
+  for (int i = (int)sv->streams.size(); i < n_streams; ++i) {
     hipStream_t s;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
       (void)hipGetLastError();
@@ -520,6 +609,8 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
     }
     sv->streams.push_back(s);
   }
+  sv->stats.express_cus = (uint64_t)sv->express_cus;
+  sv->stats.cu_masked = sv->cu_masked ? 1u : 0u;
   if (hipStreamCreateWithFlags(&sv->setup, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     for (hipStream_t x : sv->streams) (void)hipStreamDestroy(x);
@@ -616,6 +707,7 @@ jefi_status jefi_server_submit(jefi_server* sv, const jefi_request* rq, uint64_t
   r.out_dtype = rq->out_dtype;
   r.out_on_host = rq->out_on_host;
   r.n_obs = n_obs;
+  r.pairs = (uint64_t)s.n_src * (uint64_t)n_obs;
   r.t_submit = now_ns();
   s.queued++;
   sv->stats.submitted++;

@@ -228,6 +228,18 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
 }  // extern "C"
 
 namespace jefi {
+int device_cus() { return 256; }
+bool create_stream_on_cus(hipStream_t* s, int first_cu, int n_cus) {
+  if (first_cu < 0 || n_cus < 1 || first_cu + n_cus > 256) return false;
+  *s = new MockStream();
+  return true;
+}
+std::atomic<int> g_express_grid_cus{0};  // grid of the last express-lane batch
+jefi_status eval_batch_on_cus(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream,
+                              int grid_cus) {
+  g_express_grid_cus.store(grid_cus);
+  return jefi_eval_batch(probs, n, opt, stream);
+}
 hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, int, int, int n_slots, int is_f64,
                                hipStream_t s) {
   const size_t bytes = (size_t)n_slots * 4 * (size_t)src.n[0] * src.n[1] * src.n[2] * (is_f64 ? 8 : 4);
@@ -239,3 +251,5 @@ hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, i
   return hipSuccess;
 }
 }  // namespace jefi
+
+int jefi_mock_express_grid() { return jefi::g_express_grid_cus.load(); }

@@ -17,6 +17,7 @@
 extern int g_eval_sleep_us;
 extern int g_ingest_sleep_us;
 extern std::atomic<unsigned> g_last_batch_flags;
+int jefi_mock_express_grid();  // grid (compute units) of the last express-lane batch
 
 static std::atomic<int> g_fail{0};
 #define CHECK(c)                                                \
@@ -66,7 +67,7 @@ struct Pending {
 };
 
 jefi_server* make_server(size_t arena_bytes, int max_inflight, int max_queue, std::vector<char>& arena,
-                         uint32_t flags = 0) {
+                         uint32_t flags = 0, uint64_t express_pairs = 0) {
   arena.assign(arena_bytes, 0);
   jefi_server_config cfg;
   std::memset(&cfg, 0, sizeof cfg);
@@ -77,6 +78,7 @@ jefi_server* make_server(size_t arena_bytes, int max_inflight, int max_queue, st
   cfg.max_batch = 64;
   cfg.max_queue = max_queue;
   cfg.flags = flags;
+  cfg.express_pairs = express_pairs;
   jefi_server* sv = nullptr;
   CHECK(jefi_server_create(&cfg, &sv) == JEFI_OK);
   return sv;
@@ -172,6 +174,39 @@ void concurrent_submitters() {
   CHECK(st.batches >= 1 && st.max_batch >= 2);
   std::printf("concurrent: %llu batches, largest %llu\n", (unsigned long long)st.batches,
               (unsigned long long)st.max_batch);
+  CHECK(jefi_server_destroy(sv) == JEFI_OK);
+}
+
+// An express lane for requests of at most 64 pairs: on sessions of 2^3
+// cells, 1^3 and 2^3 observation points go express, 3^3 and 4^3 regular;
+// every session mixes both kinds, so each session's pushes and evaluations
+// must keep their order across the lanes.
+void express_lane() {
+  std::vector<char> arena;
+  jefi_server* sv = make_server(64 << 20, 2, 65536, arena, 0, 64);
+  g_eval_sleep_us = 100;
+  std::vector<Session> ss = {{21, 2, 0}, {22, 2, 0}, {23, 2, 0}};
+  open_sessions(sv, ss, 3);
+  std::mt19937 rng(7);
+  std::vector<Pending> ps(120);
+  int small = 0;
+  for (int i = 0; i < 120; ++i) {
+    const int edge = 1 + (int)(rng() % 4);  // 8 * edge^3 pairs: 8, 64 express; 216, 512 regular
+    small += edge <= 2;
+    submit(sv, ss[rng() % ss.size()], ps[(size_t)i], edge);
+    // paced, so that the queue stays shorter than a batch (a backlog
+    // switches the express lane off)
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+  for (Pending& p : ps) check_result(sv, p);
+  jefi_server_stats st;
+  CHECK(jefi_server_get_stats(sv, &st) == JEFI_OK);
+  CHECK(st.completed == 120 && st.failed == 0);
+  CHECK(st.express_batches >= 1 && st.express_batches < st.batches);
+  CHECK(st.express_cus == 16 && st.cu_masked == 1);
+  CHECK(jefi_mock_express_grid() == 16);
+  std::printf("express lane: %d small of 120 requests, %llu of %llu batches express\n", small,
+              (unsigned long long)st.express_batches, (unsigned long long)st.batches);
   CHECK(jefi_server_destroy(sv) == JEFI_OK);
 }
 
@@ -393,6 +428,7 @@ void poll_and_wait_one_ticket() {
 int main() {
   std::setvbuf(stdout, nullptr, _IONBF, 0);
   concurrent_submitters();
+  express_lane();
   eviction();
   full_queue_and_rejections();
   time_after_newest_fails_at_admission();

@@ -63,7 +63,7 @@ def _solo(J, src, hist_window, dt, newest, obs, t, prec="f32", flags=0):
 
 
 def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32", max_inflight=2,
-                blocker=False, flags=0, reserve_cus=0):
+                blocker=False, flags=0, reserve_cus=0, express_pairs=0):
     """n_req requests over n_sessions sessions, submitted back to back.
     blocker: first submit one large request of an extra session, so that
     (with max_inflight = 1) the others queue up behind it and are batched."""
@@ -74,7 +74,7 @@ def _run_stream(J, arena_bytes, n_sessions, n_req, seed, init_steps=6, prec="f32
     f64 = prec == "f64"
     ndt = np.float64 if f64 else np.float32
     sv = J.Server(arena, precision=J.JEFI_PREC_F64 if f64 else J.JEFI_PREC_F32_COMP, max_inflight=max_inflight,
-                  max_batch=64, flags=flags, reserve_cus=reserve_cus)
+                  max_batch=64, flags=flags, reserve_cus=reserve_cus, express_pairs=express_pairs)
     if blocker:
         bsrc = centred_grid((48, 48, 48), 1.6 / 48)
         bh = blob_history(bsrc, workloads.draw_blobs(np.random.default_rng(1), 3, (-0.8, 0.8)), 8, 0.8 / 48)
@@ -175,6 +175,23 @@ def test_server_with_cu_reserve():
                                              reserve_cus=32)
     assert stats["completed"] == 24 and stats["failed"] == 0
     _check_solo(J, reqs, full, n_oracle=2)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_server_express_lane(prec):
+    """Small requests in an express lane (a stream on a few reserved compute
+    units), large ones behind a blocker in the regular lane, sessions mixing
+    both: every result equals the same evaluation alone and the oracle."""
+    J = _gpu()
+    reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=5, n_req=40, seed=21, prec=prec,
+                                             max_inflight=1, blocker=True, express_pairs=200000)
+    assert stats["completed"] == 41 and stats["failed"] == 0
+    assert 1 <= stats["express_batches"] < stats["batches"], stats
+    assert stats["express_cus"] == 16
+    small = sum(1 for r in results if r.pairs <= 200000)
+    print(f"express lane ({prec}): {small} small of {len(results)} requests, {stats['express_batches']} of "
+          f"{stats['batches']} batches, CU-masked streams: {stats['cu_masked']}", flush=True)
+    _check_solo(J, reqs, full, n_oracle=3, prec=prec)
 
 
 @pytest.mark.parametrize("prec,reading", [("f32", "slope"), ("f64", "slope"), ("f32", "cubic"), ("f64", "cubic")])
