@@ -652,8 +652,37 @@ def accuracy_study(levels=(1, 2, 4, 8), cases=ACC_CASES, ref_prec_bytes=40e9):
             for key in [r for r in levels if r != top] + ["1-f32"]:
                 E, B = fields[key][t]
                 row[f"r{key}"] = {"E": round(xoy_deviation(E, ref_E), 5), "B": round(xoy_deviation(B, ref_B), 5)}
+            if kind == "constant":
+                row["continuum"] = continuum_deviations(fields, levels, t)
             res[kind][str(t)] = row
     return res
+
+
+def continuum_deviations(fields, levels, t):
+    """The constant-source sums against the continuous equations (FP64
+    quadrature) in two readings: with the switch-on shell, and without it
+    (the Coulomb and Biot-Savart fields of the box within distance t).  Also
+    the discretised sum that leaves the switch-on derivative out (the static
+    sum over the cells within distance t) against the second reading."""
+    import workloads
+    from tests.continuum import ball_sum_plane, switched_on_box_plane
+    obs = workloads.Grid((15, 15, 1), (-2.8, -2.8, 0.0), (0.4, 0.4, 0.4))
+    pts = workloads.cell_centres(obs)
+    box = ((-3.0,) * 3, (3.0,) * 3)
+    refs = switched_on_box_plane(pts, t, *box)
+    out = {}
+    for reading, (rE, rB) in refs.items():
+        row = {"max_E_xy": round(float(np.sqrt(rE[0] ** 2 + rE[1] ** 2).max()), 5),
+               "max_B_xy": round(float(np.sqrt(rB[0] ** 2 + rB[1] ** 2).max()), 5)}
+        for r in levels:
+            E, B = fields[r][t]
+            row[f"r{r}"] = {"E": round(xoy_deviation(E, rE), 5), "B": round(xoy_deviation(B, rB), 5)}
+        out[reading] = row
+    E, B = ball_sum_plane(pts, t, *box, 0.4, 0.2)
+    rE, rB = refs["no_shell"]
+    out["no_shell"]["r1_without_switch_on_derivative"] = {"E": round(xoy_deviation(E, rE), 5),
+                                                          "B": round(xoy_deviation(B, rB), 5)}
+    return out
 
 
 def run_accuracy_workload(args):

@@ -12,12 +12,17 @@ as max |(dEx, dEy)| / max |(Ex, Ey)| (the paper's norms).
   Refining the grid 1, 2, 4, 8, 16 times converges to the closed form.
 - The paper's snapshots t = 2.5, 5, 7.5 (time step 0.05): the deviation
   from the same discretisation refined 4 times shrinks as the grid is
-  refined."""
+  refined.
+- The same snapshots against the continuous equations, computed by FP64
+  quadrature (tests/continuum.py): the discretised sums converge to the
+  reading that keeps the switch-on shell; the reading without it (the
+  Coulomb and Biot-Savart fields of the box within distance t) has the
+  paper's field scale (peak 0.529 at t = 2.5) and is far from the sums."""
 import numpy as np
 import pytest
 
 import workloads
-from tests.continuum import box_fields
+from tests.continuum import box_fields, switched_on_box_plane
 
 pytestmark = pytest.mark.gpu
 
@@ -96,3 +101,26 @@ def test_paper_snapshots_converge():
         print(f"constant sources t = {t}: 15^3 deviates {d1[0]:.3%} (E) {d1[1]:.3%} (B), "
               f"30^3 {d2[0]:.3%} {d2[1]:.3%} from 60^3", flush=True)
         assert d2[0] < d1[0] and d2[1] < d1[1], (t, d1, d2)
+
+
+def test_paper_snapshots_against_the_continuum():
+    _gpu()
+    import bench
+    times = (2.5, 5.0, 7.5)
+    pts = workloads.cell_centres(_plane())
+    f = {r: bench.accuracy_fields("constant", r, times, 0.0) for r in (1, 2, 4)}
+    for t in times:
+        ref = switched_on_box_plane(pts, t, (-3.0,) * 3, (3.0,) * 3)
+        dev = {k: {r: [_xoy_dev(f[r][t][i], ref[k][i]) for i in (0, 1)] for r in f} for k in ref}
+        print(f"constant sources t = {t}: with the shell " +
+              ", ".join(f"{15 * r}^3 {d[0]:.3%} (E) {d[1]:.3%} (B)" for r, d in dev["shell"].items()) +
+              "; without it " + ", ".join(f"{15 * r}^3 {d[0]:.1%} {d[1]:.1%}" for r, d in dev["no_shell"].items()),
+              flush=True)
+        # the sums converge to the reading with the shell ...
+        assert dev["shell"][4][0] < dev["shell"][1][0] and dev["shell"][4][1] < dev["shell"][1][1], (t, dev)
+        # ... and stay far from the one without it
+        assert min(dev["no_shell"][r][0] for r in f) > 0.2, (t, dev)
+    # the reading without the shell has the paper's scale: the one-face cap
+    # field (t - h)^2 / (4 t) at h = 0.2 from a face
+    E0 = switched_on_box_plane(pts, 2.5, (-3.0,) * 3, (3.0,) * 3)["no_shell"][0]
+    assert abs(np.sqrt(E0[0] ** 2 + E0[1] ** 2).max() - 2.3 ** 2 / 10.0) < 1e-9
