@@ -169,7 +169,7 @@ const char* jefi_version(void);
 const char* jefi_last_error(void);
 void jefi_options_default(jefi_options* opt);
 
-/* ---- source history (row: history ingest) ------------------------------
+/* ---- source history ------------------------------------------------------
  * The stored history of rho and J slices the sums read at retarded times
  * (paper, section "Parameter dependence": rho and J are kept in GPU memory
  * for all relevant times and are not released between calls). */
@@ -189,8 +189,8 @@ jefi_status jefi_history_init(jefi_history* h, void* data, uint64_t bytes, const
 jefi_status jefi_history_push(jefi_history* h, const jefi_grid* src, const void* slice,
                               void* stream);
 
-/* ---- field evaluation (rows: host prelude, pair loop, tile staging,
- * reduction/epilogue) -------------------------------------------------------
+/* ---- field evaluation (section "GPU implementation": the discretised E, B
+ * and retarded-time equations, one result per observation point) ----------
  * E and B at time t on the observation grid from the last `nt` steps of the
  * history (1 <= nt <= min(capacity, newest + 1)); t must not lie after the
  * newest step (beyond FP64 rounding of t): EINVAL otherwise.  `opt` NULL =
@@ -217,7 +217,7 @@ jefi_status jefi_eval_fields_noalloc(const jefi_grid* src, const jefi_history* h
                                      const jefi_grid* obs, double t, const jefi_fields* out,
                                      const jefi_options* opt, void* stream);
 
-/* ---- batched evaluation (row: batched persistent launch) -------------------
+/* ---- batched evaluation ---------------------------------------------------
  * Many independent problems of uneven sizes in one persistent launch:
  * workgroups pull (problem, observation tile, source split) items, heaviest
  * first, from a device queue; the launch sequence (queue reset, threshold
@@ -271,11 +271,56 @@ jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_opt
 jefi_status jefi_autotune(const jefi_problem* probs, int32_t n, const jefi_options* opt, int32_t reps,
                           void* stream, int32_t* best_config, double* best_ms);
 
-/* ---- serving loop (row: serving) -----------------------------------------
+/* ---- per-step coupling with a producer ------------------------------------
+ * The paper's per-step use (section "Parameter dependence", Table 4 upper
+ * panel; the transport-code coupling of the introduction): every time step
+ * a producer hands the new rho/J slice over and takes E and B of that step
+ * back.  A coupler runs each step as: slice to the device (copy-in stream),
+ * push and evaluation at the new step's time (compute stream), E and B back
+ * to pinned host memory (copy-out stream).  Two staging slots take
+ * alternate steps, so the next step's slice travels while a step evaluates
+ * and a step's fields travel while the next one evaluates.  The coupler
+ * owns its streams and staging (pinned host and device memory for two
+ * slices and two sets of fields); the caller owns the history, which the
+ * coupler pushes into (hist->newest advances at each step call).  Use it
+ * from one thread. */
+typedef struct jefi_coupler jefi_coupler;
+
+/* Evaluations on `obs` from the last min(nt, pushed) steps of `hist`, with
+ * `opt` (NULL = defaults; its precision must match the history dtype) and
+ * fields of out_dtype.  EINVAL on bad arguments, ENOMEM when the staging
+ * cannot be allocated. */
+jefi_status jefi_coupler_create(const jefi_grid* src, jefi_history* hist, double dt, int32_t nt,
+                                const jefi_grid* obs, const jefi_options* opt, int32_t out_dtype,
+                                jefi_coupler** out);
+
+/* Enqueue the next step (absolute step hist->newest + 1, returned in *step):
+ * slice = [4][n_src] of the history dtype, in HOST memory (slice_on_host = 1:
+ * copied into pinned staging before return) or DEVICE memory (0: read by
+ * the push in stream order, so it must stay valid until the step is
+ * collected).  Asynchronous.  EBUSY while the step two back (same slot) has
+ * not been collected; EINVAL/EDEVICE as jefi_history_push and
+ * jefi_eval_fields. */
+jefi_status jefi_coupler_step(jefi_coupler* c, const void* slice, int32_t slice_on_host, int64_t* step);
+
+/* Wait for `step` and copy its E and B (HOST [3][n_obs] of out_dtype each).
+ * ENOENT if that step is not waiting to be collected. */
+jefi_status jefi_coupler_collect(jefi_coupler* c, int64_t step, void* E, void* B);
+
+/* Waits for all enqueued work, frees the coupler. */
+jefi_status jefi_coupler_destroy(jefi_coupler* c);
+
+/* ---- serving loop ----------------------------------------------------------
  * Field evaluations of many sessions (a time-stepping source each) arrive at
  * any time.  Each session keeps its history resident in a caller-provided
  * device arena (the HBM budget); each request pushes the session's next
- * slice and evaluates on its own observation grid.  A scheduler thread
+ * slice and evaluates on its own observation grid: the paper's per-step use
+ * (section "Parameter dependence", Table 4 upper panel: one slice to the
+ * device, one evaluation, E and B back, per time step).  What a session
+ * occupies follows the paper's memory count (same section, the equation for
+ * N: (lts + 1) slices of 4 values per source cell plus 6 per observation
+ * point); admission charges the ring, the slice staging and the outputs
+ * against the arena in the same way.  A scheduler thread
  * admits requests in arrival order as arena bytes and batch slots free up
  * (evicting idle sessions least-recently-used first and re-uploading their
  * history from a host copy when they return) and launches them as batched

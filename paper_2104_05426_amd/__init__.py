@@ -34,6 +34,7 @@ EXPORTS = [
     "jefi_slice_fingerprint", "jefi_eval_batch", "jefi_autotune",
     "jefi_server_create", "jefi_server_open_session", "jefi_server_submit", "jefi_server_poll",
     "jefi_server_wait", "jefi_server_close_session", "jefi_server_get_stats", "jefi_server_destroy",
+    "jefi_coupler_create", "jefi_coupler_step", "jefi_coupler_collect", "jefi_coupler_destroy",
 ]
 
 
@@ -127,6 +128,11 @@ def _load():
         "jefi_server_close_session": ([vp, C.c_uint64], C.c_int),
         "jefi_server_get_stats": ([vp, P(jefi_server_stats)], C.c_int),
         "jefi_server_destroy": ([vp], C.c_int),
+        "jefi_coupler_create": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32, P(jefi_grid),
+                                 P(jefi_options), C.c_int32, P(vp)], C.c_int),
+        "jefi_coupler_step": ([vp, vp, C.c_int32, P(C.c_int64)], C.c_int),
+        "jefi_coupler_collect": ([vp, C.c_int64, vp, vp], C.c_int),
+        "jefi_coupler_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -378,6 +384,44 @@ class Server:
     def destroy(self):
         if self.h is not None:
             st = lib.jefi_server_destroy(self.h)
+            self.h = None
+            return st
+        return JEFI_OK
+
+
+class Coupler:
+    """Thin owner of a jefi_coupler handle (the C calls do all the work):
+    per-step push + evaluation with the slice and field copies overlapped."""
+
+    def __init__(self, src, h: jefi_history, dt: float, nt: int, obs, opt: Optional[jefi_options] = None,
+                 out_dtype: int = JEFI_F32):
+        self.hist = h  # the coupler pushes into this structure
+        self.src = make_grid(src)
+        self.obs = make_grid(obs)
+        hnd = C.c_void_p()
+        _check(lib.jefi_coupler_create(C.byref(self.src), C.byref(h), float(dt), int(nt), C.byref(self.obs),
+                                       C.byref(opt) if opt is not None else None, int(out_dtype),
+                                       C.byref(hnd)))
+        self.h = hnd
+
+    def step(self, slice_):
+        """slice_: numpy [4][n_src] (host) or a device tensor; returns the step."""
+        import numpy as np
+        st = C.c_int64(0)
+        if isinstance(slice_, np.ndarray):
+            arr = np.ascontiguousarray(slice_)
+            _check(lib.jefi_coupler_step(self.h, arr.ctypes.data, 1, C.byref(st)))
+        else:
+            _check(lib.jefi_coupler_step(self.h, _ptr(slice_), 0, C.byref(st)))
+        return int(st.value)
+
+    def collect(self, step, E, B):
+        """E, B: numpy arrays [3][n_obs] of the coupler's output dtype."""
+        _check(lib.jefi_coupler_collect(self.h, int(step), E.ctypes.data, B.ctypes.data))
+
+    def destroy(self):
+        if self.h is not None:
+            st = lib.jefi_coupler_destroy(self.h)
             self.h = None
             return st
         return JEFI_OK

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjefi.so")
 SOURCES = [os.path.join(CSRC, "jefi_kernels.hip"), os.path.join(CSRC, "jefi_api.cpp"),
-           os.path.join(CSRC, "jefi_server.cpp")]
+           os.path.join(CSRC, "jefi_server.cpp"), os.path.join(CSRC, "jefi_coupler.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

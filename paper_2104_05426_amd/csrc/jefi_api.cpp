@@ -1241,6 +1241,12 @@ jefi_status eval_batch_impl(const jefi_problem* probs, int32_t n, const jefi_opt
 
 namespace jefi {
 
+jefi_status report_error(jefi_status st, const char* msg) { return fail(st, "%s", msg); }
+
+jefi_status report_hip(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+bool device_failed() { return g_device_failed.load() != 0; }
+
 int device_cus() { return launch_cus(0); }
 
 bool create_stream_on_cus(hipStream_t* s, int first_cu, int n_cus) {

@@ -138,6 +138,12 @@ hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);
 hipError_t launch_fill_zero_fields(void* E, void* B, long long n_obs, int out_f64, hipStream_t s);
 hipError_t launch_dump(const DumpParams& p, hipStream_t s);
 
+// The library's error state (jefi_last_error, the sticky device failure),
+// for the parts of the library outside jefi_api.cpp.
+jefi_status report_error(jefi_status st, const char* msg);
+jefi_status report_hip(hipError_t e, const char* what);  // sticky: every later call fails
+bool device_failed();
+
 // Compute units of the current device.
 int device_cus();
 // A non-blocking stream whose kernels run only on compute units
