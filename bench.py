@@ -714,16 +714,15 @@ PAPER_TABLE4 = {20: (1.001, 0.0004, 0.002), 60: (2.720, 0.002, 0.004), 70: (4.85
 def run_paper_steps(args):
     """Per-step time at the paper's grid sizes in three couplings:
     serial (copy in, push, evaluate, copy out, as the paper times it);
-    overlapped (step s's E/B copy out and slice s+1's copy in run on a copy
-    stream while step s+1 evaluates); device producer (the slice is made on
-    the device and pushed from there, E/B copy out overlapped)."""
+    overlapped (the library's coupler: step s's E/B copy out and slice
+    s+1's copy in run on copy streams while step s+1 evaluates); device
+    producer (the slice is made on the device and handed to the coupler
+    from there, E/B copy out overlapped)."""
     import torch
     import workloads
     import paper_2104_05426_amd as J
     lts, dt = 500, 0.05
     sizes = [20, 60, 70, 100, 160] if not args.paper_sizes else [int(v) for v in args.paper_sizes.split(",")]
-    comp = torch.cuda.current_stream()
-    copy = torch.cuda.Stream()
     out = {}
     for n in sizes:
         dx = 6.0 / n
@@ -784,39 +783,33 @@ def run_paper_steps(args):
         serial = float(parts.sum(axis=1).mean())
 
         def pipelined(device_producer):
+            # the library's coupler: slice copy-in, push + evaluation and
+            # E/B copy-out on three streams, one step in flight behind the newest
+            cp = J.Coupler(g, h, dt, lts + 1, g, opt, J.JEFI_F32)
+            hs = [host_slice[0].numpy(), host_slice[1].numpy()]
+            oE, oB = hE[0].numpy(), hB[0].numpy()
             host_make(0)
             host_make(1)
+            # one untimed step: the coupler's streams get their workspaces
+            cp.collect(cp.step(hs[0]), oE, oB)
+            k_next[0] += 1
             torch.cuda.synchronize()
-            done = [torch.cuda.Event() for _ in range(steps)]
-            arrived = [torch.cuda.Event() for _ in range(steps)]
-            copied = [torch.cuda.Event() for _ in range(steps)]
             t0 = time.perf_counter()
-            if not device_producer:
-                with torch.cuda.stream(copy):
-                    dev_slice[0].copy_(host_slice[0], non_blocking=True)
-                    arrived[0].record(copy)
+            prev = None
             for i in range(steps):
-                if i >= 2:
-                    comp.wait_event(copied[i - 2])  # E/B[i % 2] of step i - 2 are on the host
                 if device_producer:
-                    make_slice(k_next[0] + i, dev_slice[i % 2])
+                    make_slice(k_next[0] + i, dev_slice[i % 2])   # on torch's stream
+                    s = cp.step(dev_slice[i % 2], torch.cuda.current_stream())
                 else:
-                    comp.wait_event(arrived[i])
-                J.jefi_history_push(h, g, dev_slice[i % 2])
-                J.jefi_eval_fields(g, h, dt, lts + 1, g, h.newest * dt, E[i % 2], B[i % 2], opt)
-                done[i].record(comp)
-                with torch.cuda.stream(copy):
-                    if not device_producer and i + 1 < steps:
-                        copy.wait_event(done[i - 1] if i > 0 else arrived[0])
-                        dev_slice[(i + 1) % 2].copy_(host_slice[(i + 1) % 2], non_blocking=True)
-                        arrived[i + 1].record(copy)
-                    copy.wait_event(done[i])
-                    hE[i % 2].copy_(E[i % 2], non_blocking=True)
-                    hB[i % 2].copy_(B[i % 2], non_blocking=True)
-                    copied[i].record(copy)
-            torch.cuda.synchronize()
+                    s = cp.step(hs[i % 2])
+                if prev is not None:
+                    cp.collect(prev, oE, oB)
+                prev = s
+            cp.collect(prev, oE, oB)
+            dt_step = (time.perf_counter() - t0) / steps
+            cp.destroy()
             k_next[0] += steps
-            return (time.perf_counter() - t0) / steps
+            return dt_step
 
         log(f"paper-steps n={n}: serial {serial:.4f} s/step")
         over = pipelined(False)

@@ -296,12 +296,14 @@ jefi_status jefi_coupler_create(const jefi_grid* src, jefi_history* hist, double
 
 /* Enqueue the next step (absolute step hist->newest + 1, returned in *step):
  * slice = [4][n_src] of the history dtype, in HOST memory (slice_on_host = 1:
- * copied into pinned staging before return) or DEVICE memory (0: read by
- * the push in stream order, so it must stay valid until the step is
- * collected).  Asynchronous.  EBUSY while the step two back (same slot) has
- * not been collected; EINVAL/EDEVICE as jefi_history_push and
- * jefi_eval_fields. */
-jefi_status jefi_coupler_step(jefi_coupler* c, const void* slice, int32_t slice_on_host, int64_t* step);
+ * copied into pinned staging before return; `stream` unused) or DEVICE
+ * memory (0: the push waits for the work enqueued on the producer's
+ * `stream` (a hipStream_t, NULL = the null stream) so far, and reads the
+ * slice then, so it must stay unchanged until the step is collected).
+ * Asynchronous.  EBUSY while the step two back (same slot) has not been
+ * collected; EINVAL/EDEVICE as jefi_history_push and jefi_eval_fields. */
+jefi_status jefi_coupler_step(jefi_coupler* c, const void* slice, int32_t slice_on_host, void* stream,
+                              int64_t* step);
 
 /* Wait for `step` and copy its E and B (HOST [3][n_obs] of out_dtype each).
  * ENOENT if that step is not waiting to be collected. */

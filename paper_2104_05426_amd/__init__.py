@@ -130,7 +130,7 @@ def _load():
         "jefi_server_destroy": ([vp], C.c_int),
         "jefi_coupler_create": ([P(jefi_grid), P(jefi_history), C.c_double, C.c_int32, P(jefi_grid),
                                  P(jefi_options), C.c_int32, P(vp)], C.c_int),
-        "jefi_coupler_step": ([vp, vp, C.c_int32, P(C.c_int64)], C.c_int),
+        "jefi_coupler_step": ([vp, vp, C.c_int32, vp, P(C.c_int64)], C.c_int),
         "jefi_coupler_collect": ([vp, C.c_int64, vp, vp], C.c_int),
         "jefi_coupler_destroy": ([vp], C.c_int),
     }
@@ -404,15 +404,16 @@ class Coupler:
                                        C.byref(hnd)))
         self.h = hnd
 
-    def step(self, slice_):
-        """slice_: numpy [4][n_src] (host) or a device tensor; returns the step."""
+    def step(self, slice_, stream=None):
+        """slice_: numpy [4][n_src] (host) or a device tensor made on `stream`
+        (default: torch's current stream); returns the step."""
         import numpy as np
         st = C.c_int64(0)
         if isinstance(slice_, np.ndarray):
             arr = np.ascontiguousarray(slice_)
-            _check(lib.jefi_coupler_step(self.h, arr.ctypes.data, 1, C.byref(st)))
+            _check(lib.jefi_coupler_step(self.h, arr.ctypes.data, 1, None, C.byref(st)))
         else:
-            _check(lib.jefi_coupler_step(self.h, _ptr(slice_), 0, C.byref(st)))
+            _check(lib.jefi_coupler_step(self.h, _ptr(slice_), 0, _stream_ptr(stream), C.byref(st)))
         return int(st.value)
 
     def collect(self, step, E, B):

@@ -22,7 +22,7 @@ struct Slot {
   void* dev_in = nullptr;    // device copy of the slice
   void* pin_out = nullptr;   // pinned E then B
   void* dev_out = nullptr;   // device E then B
-  hipEvent_t in_ready = nullptr;   // slice on the device (copy-in stream)
+  hipEvent_t in_ready = nullptr;   // slice on the device (copy-in or producer stream)
   hipEvent_t pushed = nullptr;     // push done: dev_in (or the caller's buffer) free again
   hipEvent_t evaluated = nullptr;  // E and B on the device (compute stream)
   hipEvent_t out_ready = nullptr;  // E and B in pin_out; dev_out free again
@@ -116,7 +116,8 @@ jefi_status jefi_coupler_create(const jefi_grid* src, jefi_history* hist, double
   return JEFI_OK;
 }
 
-jefi_status jefi_coupler_step(jefi_coupler* c, const void* slice, int32_t slice_on_host, int64_t* step) {
+jefi_status jefi_coupler_step(jefi_coupler* c, const void* slice, int32_t slice_on_host, void* stream,
+                              int64_t* step) {
   if (jefi::device_failed()) return jefi::report_error(JEFI_EDEVICE, "an earlier HIP failure is sticky");
   if (!c || !slice) return jefi::report_error(JEFI_EINVAL, "coupler step: NULL argument");
   const long long s = c->hist->newest + 1;
@@ -138,9 +139,11 @@ jefi_status jefi_coupler_step(jefi_coupler* c, const void* slice, int32_t slice_
     if ((e = hipStreamWaitEvent(c->s_comp, sl.in_ready, 0)) != hipSuccess) return jefi::report_hip(e, "coupler step");
     dev_slice = sl.dev_in;
   } else {
-    // a device slice of the caller's, read by the push in stream order; the
-    // pinned and device staging of the slot stay unused
-    if ((e = hipEventRecord(sl.in_ready, c->s_comp)) != hipSuccess) return jefi::report_hip(e, "coupler step");
+    // a device slice of the caller's: the push waits for the work enqueued
+    // on the producer's stream so far; the slot's staging stays unused
+    if ((e = hipEventRecord(sl.in_ready, (hipStream_t)stream)) != hipSuccess)
+      return jefi::report_hip(e, "coupler step");
+    if ((e = hipStreamWaitEvent(c->s_comp, sl.in_ready, 0)) != hipSuccess) return jefi::report_hip(e, "coupler step");
   }
   // E and B of the step two back must have left the device buffer
   if (sl.used && (e = hipStreamWaitEvent(c->s_comp, sl.out_ready, 0)) != hipSuccess)

@@ -136,3 +136,34 @@ def test_dump_validation():
     st = J.lib.jefi_slice_index_dump(C.byref(src), 0, 0.05, 7, 0.0, C.byref(obs), 0.3, None,
                                      C.c_void_p(0x10), None)
     assert st == J.JEFI_EINVAL
+
+
+def test_coupler_validation():
+    """Bad coupler arguments are rejected before any stream, event or
+    allocation is made."""
+    import paper_2104_05426_amd as J
+    src, obs = J.make_grid(_grid()), J.make_grid(_grid())
+    h = J.jefi_history(C.c_void_p(0x1000), J.JEFI_F32, 8, -1, 0.0)
+    out = C.c_void_p()
+
+    def create(**kw):
+        a = dict(src=C.byref(src), hist=C.byref(h), dt=0.05, nt=4, obs=C.byref(obs), out_dtype=J.JEFI_F32,
+                 out=C.byref(out))
+        a.update(kw)
+        return J.lib.jefi_coupler_create(a["src"], a["hist"], a["dt"], a["nt"], a["obs"], None, a["out_dtype"],
+                                         a["out"])
+    assert create(src=None) == J.JEFI_EINVAL
+    assert create(out=None) == J.JEFI_EINVAL
+    assert create(nt=0) == J.JEFI_EINVAL
+    assert create(nt=9) == J.JEFI_EINVAL
+    assert create(dt=0.0) == J.JEFI_EINVAL
+    assert create(out_dtype=5) == J.JEFI_EINVAL
+    bad = J.make_grid(_grid((0, 4, 4)))
+    assert create(obs=C.byref(bad)) == J.JEFI_EINVAL
+    h.dtype = 3
+    assert create() == J.JEFI_EINVAL
+    assert out.value is None
+    st = C.c_int64(0)
+    assert J.lib.jefi_coupler_step(None, C.c_void_p(0x10), 1, None, C.byref(st)) == J.JEFI_EINVAL
+    assert J.lib.jefi_coupler_collect(None, 0, C.c_void_p(0x10), C.c_void_p(0x10)) == J.JEFI_EINVAL
+    assert J.lib.jefi_coupler_destroy(None) == J.JEFI_EINVAL
