@@ -27,6 +27,7 @@ SCREENED = -(2 ** 31)
 STENCIL_SLOPE = 1  # time derivative = slope of the linear interpolant
 STENCIL_HOLD = 2   # history before the oldest slice = the oldest slice
 STENCIL_CUBIC = 4  # cubic through slices k-2 .. k+1 (not with STENCIL_SLOPE)
+STENCIL_CUT = 8    # history starts at the oldest slice (not with STENCIL_HOLD)
 
 
 class _Grid(C.Structure):
@@ -124,8 +125,10 @@ def eval_fields(src, obs, hist: np.ndarray, dt: float, t: float, t0: float = 0.0
     slope of the interpolant (``STENCIL_SLOPE``), bit 1 = history before
     the oldest slice held at its values (``STENCIL_HOLD``), bit 2 = cubic
     time interpolation through slices k-2 .. k+1 (``STENCIL_CUBIC``, not
-    with bit 0); 0 = the
-    interpolated backward difference and a zero past."""
+    with bit 0), bit 3 = the history starts at the oldest slice: earlier
+    retarded times contribute nothing and no derivative is taken across the
+    start (``STENCIL_CUT``, not with bit 1); 0 = the interpolated backward
+    difference and a zero past."""
     lib = _load()
     h = np.ascontiguousarray(hist, dtype=np.float64)
     nt = int(h.shape[0])

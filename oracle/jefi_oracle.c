@@ -38,7 +38,13 @@
  *     derivative divided by dt).  Its nodes end at k+1, so it reads no slice
  *     the linear stencil does not reach at the top, and a pair whose k+1
  *     lies before the oldest slice still contributes nothing.  It cannot be
- *     combined with bit 0.
+ *     combined with bit 0;
+ *   - bit 3: the history starts at the oldest slice: a pair whose retarded
+ *     time precedes it (k < 0) contributes nothing, and stencils that reach
+ *     before it read the oldest slice's values (as bit 1), so no time
+ *     derivative is taken across the start.  For sources switched on at the
+ *     oldest slice this leaves out the switch-on shell that the zero past
+ *     gives (the step's derivative).  It cannot be combined with bit 1.
  * None of them changes the slice index k or the screening decision.
  *   - the slice index is k = a_i + floor(u), u = a_f - R*inv_cdt with the
  *     host split a = (t - t0)/dt - s_old = a_i + a_f, all in FP64 with no
@@ -223,8 +229,9 @@ int orc_eval(const orc_grid* src, const orc_grid* obs, const double* hist, int32
              const int64_t* sel, int64_t n_sel, double* E, double* B, int32_t threads,
              int32_t stencil) {
   if (!src || !obs || !hist || !E || !B || !delta) return -1;
-  if (stencil < 0 || stencil > 7 || (stencil & 5) == 5) return -1;
-  const int slope = (stencil & 1) != 0, hold = (stencil & 2) != 0, cubic = (stencil & 4) != 0;
+  if (stencil < 0 || stencil > 15 || (stencil & 5) == 5 || (stencil & 10) == 10) return -1;
+  const int slope = (stencil & 1) != 0, cubic = (stencil & 4) != 0, cut = (stencil & 8) != 0;
+  const int hold = (stencil & 2) != 0 || cut; /* slices before the oldest read as the oldest */
   if (!orc_grid_ok(src) || !orc_grid_ok(obs)) return -1;
   orc_time tm;
   int rc = orc_time_prelude(t, t0, dt, newest, nt, c, &tm);
@@ -251,6 +258,7 @@ int orc_eval(const orc_grid* src, const orc_grid* obs, const double* hist, int32
       int64_t k;
       orc_centre(src, s, rs);
       if (orc_pair(ro, rs, delta, &tm, d, &R, &k, &f)) continue;
+      if (cut && k < 0) continue;    /* retarded time before the start of the history */
       if (k < -1 && !hold) continue; /* the whole stencil lies before the oldest slice */
       if ((f != 0.0 || slope || cubic) && k + 1 > (int64_t)nt - 1) { bad |= 2; continue; }
       double val[4], der[4];

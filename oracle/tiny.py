@@ -10,8 +10,10 @@ differences interpolated the same way, zero history before the oldest slice,
 the slice index from the FP64 split a = a_i + a_f, and the cube screening.
 The alternative time-stencil readings (derivative as the slope of the
 interpolant; history before the oldest slice held at its values; cubic time
-interpolation through slices k-2 .. k+1) are selected by the same
-``stencil`` bits as the C oracle.  The cubic is written here in Newton's
+interpolation through slices k-2 .. k+1; a history that starts at the oldest
+slice, so that earlier retarded times contribute nothing and no derivative is
+taken across the start) are selected by the same ``stencil`` bits as the C
+oracle.  The cubic is written here in Newton's
 forward-difference form, the C oracle uses Lagrange weights.
 
 Cost is O(n_obs * n_src * 4) Python operations: keep n_obs * n_src <= ~3e5.
@@ -66,12 +68,15 @@ def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
                 sel: Sequence[int] | None = None, stencil: int = 0):
     """E, B as lists [3][n_out] of floats.  ``hist[j][ch][s]`` with j = 0
     the oldest of nt slices.  ``stencil`` bit 0: slope derivative; bit 1:
-    held past; bit 2: cubic."""
+    held past; bit 2: cubic; bit 3: history starting at the oldest slice."""
     slope = bool(stencil & 1)
-    hold = bool(stencil & 2)
     cubic = bool(stencil & 4)
+    cut = bool(stencil & 8)
     if slope and cubic:
         raise ValueError("the slope and cubic readings exclude each other")
+    if cut and stencil & 2:
+        raise ValueError("a held past and a history starting at the oldest slice exclude each other")
+    hold = bool(stencil & 2) or cut  # stencils reaching before the start read the oldest slice
     nt = len(hist)
     ai, af, inv_cdt = time_split(t, t0, dt, newest, nt, c)
     ns = src.n[0] * src.n[1] * src.n[2]
@@ -96,6 +101,8 @@ def eval_fields(src, obs, hist, dt, t, t0, newest, c=1.0, delta=(0.0, 0.0, 0.0),
             if dec is None:
                 continue
             d, R, k, f = dec
+            if cut and k < 0:
+                continue  # retarded time before the start of the history
             if k < -1 and not hold:
                 continue
             # value and backward difference at the retarded time, both as

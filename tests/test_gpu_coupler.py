@@ -126,3 +126,42 @@ def test_coupler_slot_rules():
     assert np.all(np.isfinite(E)) and np.all(np.isfinite(B))
     assert cp.destroy() == J.JEFI_OK
     del store
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_device_producer_on_its_own_stream(prec):
+    """A producer that writes each slice on a stream of its own, after a
+    delay, into one of two reused buffers: the coupler's push waits for that
+    stream, so the coupled steps still equal the serial loop bit for bit."""
+    J, torch = _gpu()
+    src, obs, dt, hist = _setup()
+    serial = _serial(J, torch, src, obs, dt, hist, prec)
+    hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
+    ndt = np.float64 if prec == "f64" else np.float32
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP)
+    store, h = J.upload_history(src, hist[:N_INIT], hdt, capacity=CAP)
+    cp = J.Coupler(src, h, dt, CAP, obs, opt, out_dtype=hdt)
+    staged = [torch.as_tensor(hist[N_INIT + k], dtype=tdt).cuda() for k in range(N_STEPS)]
+    buf = [torch.zeros_like(staged[0]) for _ in range(2)]
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    out, steps = [], []
+    for k in range(N_STEPS):
+        with torch.cuda.stream(side):
+            torch.cuda._sleep(2_000_000)   # the producer is still busy when the step is enqueued
+            buf[k % 2].copy_(staged[k])
+        steps.append(cp.step(buf[k % 2], side))
+        if k >= 1:
+            E = np.empty((3, obs.size), ndt)
+            B = np.empty((3, obs.size), ndt)
+            cp.collect(steps[k - 1], E, B)   # also frees buf[(k - 1) % 2] for step k + 1
+            out.append((E, B))
+    E = np.empty((3, obs.size), ndt)
+    B = np.empty((3, obs.size), ndt)
+    cp.collect(steps[-1], E, B)
+    out.append((E, B))
+    assert cp.destroy() == J.JEFI_OK
+    for k, ((Es, Bs), (Ec, Bc)) in enumerate(zip(serial, out)):
+        assert np.array_equal(Es, Ec) and np.array_equal(Bs, Bc), (prec, k)
+    del store, staged, buf

@@ -39,6 +39,9 @@ MUTATIONS = {
                                    "double h = orc_h(hist, ns, k - 3 + i, ch, s, hold);"),
     "held past keeps h(-1) = 0 in D_0": ("double hm = orc_h(hist, ns, k - 1, ch, s, hold);",
                                          "double hm = k - 1 < 0 ? 0.0 : orc_h(hist, ns, k - 1, ch, s, hold);"),
+    "history start keeps pairs at k = -1": ("if (cut && k < 0) continue;", "if (cut && k < -1) continue;"),
+    "history start reads a zero past": ("const int hold = (stencil & 2) != 0 || cut;",
+                                        "const int hold = (stencil & 2) != 0;"),
 }
 
 PIN_CALLS = [
@@ -56,6 +59,8 @@ PIN_CALLS = [
     lambda: pins.test_held_past_constant_history_is_static_at_any_time(2),
     lambda: pins.test_held_past_linear_history(2),
     lambda: pins.test_held_past_linear_history(3),
+    lambda: pins.test_history_start_linear_history(8),
+    lambda: pins.test_history_start_constant_sources_are_the_static_ball_sum(8),
     pins.test_voxelised_uniform_sphere_is_coulomb_outside,
     pins.test_uniform_charge_and_current_box_match_the_continuum,
     pins.test_cubic_history_is_reproduced_exactly,

@@ -377,6 +377,79 @@ def test_held_past_linear_history(stencil):
     assert np.allclose(E, E_ref, rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("stencil", [8, 9])
+def test_history_start_linear_history(stencil):
+    """The history starts at the oldest slice (stencil bit 3): rho = a + b t
+    from t_old on.  A pair whose retarded time precedes t_old contributes
+    exactly nothing.  After it: value a + b t_r; derivative f b on the
+    first interval (D_0 = 0: no difference is taken across the start) and
+    b later; the slope reading (bit 0) gives b from t_old on."""
+    a, b = 0.7, -1.3
+    dt, nt, s_old = 0.05, 8, 3
+    t_old = s_old * dt
+    newest = s_old + nt - 1
+    t = newest * dt
+    hist = _hist_from(lambda tt: [a + b * tt, 0.0, 0.0, 0.0], nt, s_old, dt)
+    src = _single_cell(h=(0.1, 0.1, 0.1))
+    Rs = t - (t_old + np.array([-0.31, -0.12, -0.037, -0.004, 0.011, 0.029, 0.047, 0.09, 0.2]))
+    E = np.zeros((3, len(Rs)))
+    for i, R in enumerate(Rs):
+        g = Grid((1, 1, 1), (R * 0.36, R * 0.48, R * 0.8), (0.1, 0.1, 0.1))
+        e, bb = oracle.eval_fields(src, g, hist, dt, t=t, newest=newest, screen=(0, 0, 0), stencil=stencil)
+        E[:, i] = e[:, 0]
+        assert np.all(bb == 0.0)
+    d = np.stack([Rs * 0.36, Rs * 0.48, Rs * 0.8])
+    Rr = np.linalg.norm(d, axis=0)
+    tr = t - Rr
+    pos = (tr - t_old) / dt
+    f = pos - np.floor(pos)
+    live = tr >= t_old
+    first = live & (tr < t_old + dt)
+    val = np.where(live, a + b * tr, 0.0)
+    if stencil & 1:
+        der = np.where(live, b, 0.0)
+    else:
+        der = np.where(tr >= t_old + dt, b, np.where(first, f * b, 0.0))
+    assert first.sum() == 3 and (~live).sum() == 4
+    E_ref = (1e-3 / FOUR_PI) * (d * val / Rr ** 3 + d * der / Rr ** 2)
+    assert np.allclose(E, E_ref, rtol=1e-11, atol=0)
+    assert np.all(E[:, ~live] == 0.0)
+
+
+@pytest.mark.parametrize("stencil", [8, 9, 12])
+def test_history_start_constant_sources_are_the_static_ball_sum(stencil):
+    """Constant rho and J from the oldest slice on, history starting there:
+    every pair whose source lies within c (t - t_old) of the observation
+    point carries the static Coulomb / Biot-Savart term, every other pair
+    nothing (no switch-on shell).  Against that sum written out directly."""
+    from tests.continuum import ball_sum_plane
+    lo, hi = (-0.6, -0.6, -0.6), (0.6, 0.6, 0.6)
+    cell = 0.2
+    src = Grid((6, 6, 6), (-0.5, -0.5, -0.5), (cell,) * 3)
+    obs = Grid((3, 3, 1), (-0.37, -0.21, 0.13), (0.41, 0.29, 0.2))  # clear of ties with cell edges
+    dt, nt = 0.05, 40
+    hist = _hist_from(lambda tt: [1.0, 1.0, 1.0, 1.0], nt, 0, dt, n_src=src.size)
+    pts = _centres(obs)
+    for t in (0.27, 0.61, 1.13):
+        E, B = oracle.eval_fields(src, obs, hist, dt, t=t, newest=nt - 1, screen=(0.1, 0.1, 0.1), stencil=stencil)
+        E_ref, B_ref = ball_sum_plane(pts, t, lo, hi, cell, 0.1)
+        # the ball sum's B is J x E_coulomb; the Jefimenko B is -(1/4pi) sum d x J / R^3, the same
+        assert np.allclose(E, E_ref, rtol=1e-12, atol=1e-15), t
+        assert np.allclose(B, B_ref, rtol=1e-12, atol=1e-15), t
+        # the zero past adds the switch-on shell
+        E0, _ = oracle.eval_fields(src, obs, hist, dt, t=t, newest=nt - 1, screen=(0.1, 0.1, 0.1))
+        assert np.abs(E0 - E_ref).max() > 1e-3 * np.abs(E_ref).max(), t
+
+
+def test_history_start_and_held_past_exclude_each_other():
+    src = _single_cell()
+    obs = _obs_points()
+    hist = np.zeros((4, 4, 1))
+    for st in (oracle.STENCIL_HOLD | oracle.STENCIL_CUT, 16):
+        with pytest.raises(Exception):
+            oracle.eval_fields(src, obs, hist, 0.05, t=0.15, screen=(0, 0, 0), stencil=st)
+
+
 def _sphere_quadrature(n_theta=24, n_phi=48):
     x, w = np.polynomial.legendre.leggauss(n_theta)
     phi = (np.arange(n_phi) + 0.5) * (2 * math.pi / n_phi)
@@ -590,7 +663,7 @@ def test_c_oracle_matches_pure_python_on_random_tiny_problems(seed):
     assert np.array_equal(d1, d2)
 
 
-@pytest.mark.parametrize("seed,stencil", [(s, st) for s in range(4) for st in (1, 2, 3, 4, 6)])
+@pytest.mark.parametrize("seed,stencil", [(s, st) for s in range(4) for st in (1, 2, 3, 4, 6, 8, 9, 12)])
 def test_c_oracle_matches_pure_python_stencil_readings(seed, stencil):
     rng = np.random.default_rng(300 + seed)
     src, obs, hist, dt, t, t0, newest, c, screen = _random_problem(rng)
