@@ -575,9 +575,10 @@ ACC_CASES = {
 }
 
 
-def accuracy_fields(kind, r, times, obs_z, prec="f64"):
+def accuracy_fields(kind, r, times, obs_z, prec="f64", flags=0):
     """E, B [3][225] on the XOY plane at each time, from the paper's source
-    on a (15 r)^3 grid with time step 0.05 / r; returns {t: (E, B)}."""
+    on a (15 r)^3 grid with time step 0.05 / r; returns {t: (E, B)}.
+    ``flags``: time-stencil reading (JEFI_FLAG_*), default the zero past."""
     import torch
     import workloads
     import paper_2104_05426_amd as J
@@ -605,6 +606,7 @@ def accuracy_fields(kind, r, times, obs_z, prec="f64"):
         J.jefi_history_push(h, src, slice_)
     opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP,
                                  screen=(0.2, 0.2, 0.2))
+    opt.flags = flags
     out = {}
     for t in times:
         E = torch.empty((3, obs.size), dtype=torch.float64, device="cuda")
@@ -643,6 +645,10 @@ def accuracy_study(levels=(1, 2, 4, 8), cases=ACC_CASES, ref_prec_bytes=40e9):
             fields[r] = accuracy_fields(kind, r, cfg["times"], cfg["obs_z"], prec)
             log(f"accuracy {kind} r={r} ({n}^3, {slots} slices, {prec}): {time.perf_counter() - t0:.1f} s")
         fields["1-f32"] = accuracy_fields(kind, 1, cfg["times"], cfg["obs_z"], "f32")
+        if kind == "constant":
+            # the reading that leaves the switch-on shell out (history starting at t = 0)
+            for r in [v for v in levels if v <= 4]:
+                fields[f"cut{r}"] = accuracy_fields(kind, r, cfg["times"], cfg["obs_z"], "f64", J.JEFI_FLAG_PAST_CUT)
         top = max(levels)
         res[kind] = {}
         for t in cfg["times"]:
@@ -682,6 +688,11 @@ def continuum_deviations(fields, levels, t):
     rE, rB = refs["no_shell"]
     out["no_shell"]["r1_without_switch_on_derivative"] = {"E": round(xoy_deviation(E, rE), 5),
                                                           "B": round(xoy_deviation(B, rB), 5)}
+    # the library's history-start reading (JEFI_FLAG_PAST_CUT) against the same
+    for key in sorted(k for k in fields if str(k).startswith("cut")):
+        E, B = fields[key][t]
+        out["no_shell"][f"{key}_history_start"] = {"E": round(xoy_deviation(E, rE), 5),
+                                                   "B": round(xoy_deviation(B, rB), 5)}
     return out
 
 

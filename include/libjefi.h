@@ -111,9 +111,9 @@ typedef struct {
   int32_t screen_set;    /* 0: half the source spacing per axis (default) */
   int32_t precision;     /* jefi_precision (default JEFI_PREC_F32_COMP) */
   uint32_t flags;        /* at most one JEFI_FLAG_INDEX_* value, at most one of
-                            JEFI_FLAG_DERIV_SLOPE and JEFI_FLAG_TIME_CUBIC, and
-                            JEFI_FLAG_PAST_HOLD; other bits and combinations are
-                            rejected (EINVAL) */
+                            JEFI_FLAG_DERIV_SLOPE and JEFI_FLAG_TIME_CUBIC, and at
+                            most one of JEFI_FLAG_PAST_HOLD and JEFI_FLAG_PAST_CUT;
+                            other bits and combinations are rejected (EINVAL) */
   int32_t tile_config;   /* launch shape: 0 = automatic (autotuned table, else a size
                             rule: 8x8x8 tiles from 32768 observation points on, taken
                             over the mean problem of a batch), 1 = 8x8x8 observation
@@ -145,8 +145,8 @@ enum {
  * (h_k - h_(k-1))/dt, and the history is zero before the oldest slice of the
  * window (pairs whose stencil lies wholly before it contribute nothing).
  * These flags select the alternatives, in any combination with each other
- * (except JEFI_FLAG_DERIV_SLOPE with JEFI_FLAG_TIME_CUBIC) and with an index
- * flag:
+ * (except JEFI_FLAG_DERIV_SLOPE with JEFI_FLAG_TIME_CUBIC, and
+ * JEFI_FLAG_PAST_HOLD with JEFI_FLAG_PAST_CUT) and with an index flag:
  *   JEFI_FLAG_DERIV_SLOPE: the derivative is the slope of the linear
  *     interpolant on the interval that holds t_r, (h_(k+1) - h_k)/dt.
  *   JEFI_FLAG_PAST_HOLD: before the oldest slice of the window the history
@@ -157,12 +157,20 @@ enum {
  *     cubic through slices k-2, k-1, k, k+1 (exact for sources cubic in
  *     time).  Its nodes end at k+1, like the linear stencil's, so the same
  *     pairs are live and no slice after the newest is read.
+ *   JEFI_FLAG_PAST_CUT: the history starts at the oldest slice of the
+ *     window: a pair whose retarded time precedes it (k < 0) contributes
+ *     nothing, and stencils that reach before it read its values, so no time
+ *     derivative is taken across the start.  For sources switched on at the
+ *     oldest slice this drops the shell that the step's derivative puts on
+ *     the light cone; it is the reading under which the constant-source
+ *     comparison (section "Constant sources") shows the paper's field scale.
  * None of them changes the slice index k, the screening decision or the
  * fingerprint (jefi_slice_fingerprint, jefi_slice_index_dump). */
 enum {
   JEFI_FLAG_DERIV_SLOPE = 4,
   JEFI_FLAG_PAST_HOLD = 8,
-  JEFI_FLAG_TIME_CUBIC = 16
+  JEFI_FLAG_TIME_CUBIC = 16,
+  JEFI_FLAG_PAST_CUT = 32
 };
 
 const char* jefi_version(void);

@@ -20,7 +20,7 @@ JEFI_EINVAL, JEFI_ENOMEM, JEFI_EDEVICE, JEFI_EBUSY, JEFI_ENOENT, JEFI_ETOOLARGE 
 JEFI_F32, JEFI_F64 = 0, 1
 JEFI_PREC_F64, JEFI_PREC_F32_COMP = 0, 1
 JEFI_FLAG_INDEX_GUARD, JEFI_FLAG_INDEX_TABLE = 1, 2
-JEFI_FLAG_DERIV_SLOPE, JEFI_FLAG_PAST_HOLD, JEFI_FLAG_TIME_CUBIC = 4, 8, 16
+JEFI_FLAG_DERIV_SLOPE, JEFI_FLAG_PAST_HOLD, JEFI_FLAG_TIME_CUBIC, JEFI_FLAG_PAST_CUT = 4, 8, 16, 32
 INT32_MIN = -(2 ** 31)
 
 STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EBUSY",

@@ -137,14 +137,15 @@ jefi_status resolve_options(const jefi_options* opt, const jefi_grid* src, Resol
   if (opt->reserve_cus < 0 || opt->reserve_cus > 1024)
     return fail(JEFI_EINVAL, "reserve_cus %d (0 .. 1024)", opt->reserve_cus);
   const unsigned known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE |
-                         JEFI_FLAG_PAST_HOLD | JEFI_FLAG_TIME_CUBIC;
+                         JEFI_FLAG_PAST_HOLD | JEFI_FLAG_TIME_CUBIC | JEFI_FLAG_PAST_CUT;
   const unsigned idx = opt->flags & (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE);
   const unsigned slope_cubic = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
+  const unsigned pasts = JEFI_FLAG_PAST_HOLD | JEFI_FLAG_PAST_CUT;
   if ((opt->flags & ~known) != 0 || idx == (JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE) ||
-      (opt->flags & slope_cubic) == slope_cubic)
+      (opt->flags & slope_cubic) == slope_cubic || (opt->flags & pasts) == pasts)
     return fail(JEFI_EINVAL,
                 "flags 0x%x (at most one JEFI_FLAG_INDEX_* value, at most one of JEFI_FLAG_DERIV_SLOPE "
-                "and JEFI_FLAG_TIME_CUBIC, and JEFI_FLAG_PAST_HOLD)",
+                "and JEFI_FLAG_TIME_CUBIC, at most one of JEFI_FLAG_PAST_HOLD and JEFI_FLAG_PAST_CUT)",
                 opt->flags);
   r->flags = opt->flags;
   r->c = opt->c;
@@ -362,7 +363,8 @@ jefi_status make_plan(const jefi_grid* src, const jefi_grid* obs, int nt, double
   plan->empty = p.n_tiles == 0 || p.n_bricks == 0;
   p.a_i = ts.a_i <= -2 ? -2 : (int)ts.a_i;
   p.stencil = ((r.flags & JEFI_FLAG_DERIV_SLOPE) ? kStencilSlope : 0) | (hold ? kStencilHold : 0) |
-              ((r.flags & JEFI_FLAG_TIME_CUBIC) ? kStencilCubic : 0);
+              ((r.flags & JEFI_FLAG_TIME_CUBIC) ? kStencilCubic : 0) |
+              ((r.flags & JEFI_FLAG_PAST_CUT) ? kStencilCut : 0);
   p.a_f = ts.a_f;
   p.inv_cdt = ts.inv_cdt;
   p.inv_dt = 1.0 / dt;

@@ -30,10 +30,13 @@ struct GridD {
 // Everything a pair-kernel launch needs; passed by value.
 // Time-stencil readings (pair kernels): derivative as the slope of the
 // linear interpolant; history before the oldest slice held at its values;
-// cubic time interpolation through slices k-2 .. k+1.
+// cubic time interpolation through slices k-2 .. k+1; a history that starts
+// at the oldest slice (earlier retarded times contribute nothing, stencils
+// reaching before it read it).
 constexpr int kStencilSlope = 1;
 constexpr int kStencilHold = 2;
 constexpr int kStencilCubic = 4;
+constexpr int kStencilCut = 8;
 
 struct PairParams {
   GridD src, obs;
@@ -73,8 +76,8 @@ struct PairParams {
   double pref;           // dOmega / (4 pi)
   unsigned long long* fp;  // fingerprint output [n_obs][4]
   int direct;            // 1: one split, the pair kernel writes E/B itself
-  int stencil;           // kStencilSlope | kStencilHold, or 0 (interpolated backward
-                         // differences, zero history before the oldest slice)
+  int stencil;           // kStencil* bits, or 0 (interpolated backward differences,
+                         // zero history before the oldest slice)
 };
 
 struct EpilogueParams {

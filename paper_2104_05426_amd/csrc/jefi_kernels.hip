@@ -152,7 +152,7 @@ __device__ __forceinline__ void two_sum_acc(float& s, float& c, float x) {
 // before slice 0 zero or (held past) slice 0's values.
 template <class PP>
 __device__ __forceinline__ float4 ring4(const float* ring, const PP& p, int j, int b, int c) {
-  if (j < 0 && (p.stencil & kStencilHold)) j = 0;  // held past: slice 0 extends backwards
+  if (j < 0 && (p.stencil & (kStencilHold | kStencilCut))) j = 0;  // slice 0 extends backwards
   if (j < 0 || j > p.nt - 1) return make_float4(0.f, 0.f, 0.f, 0.f);
   int slot = p.slot_base + j;
   if (slot >= p.capacity) slot -= p.capacity;
@@ -162,7 +162,7 @@ __device__ __forceinline__ float4 ring4(const float* ring, const PP& p, int j, i
 template <class PP>
 __device__ __forceinline__ void ring4(const double* ring, const PP& p, int j, int b, int c,
                                       double out[4]) {
-  if (j < 0 && (p.stencil & kStencilHold)) j = 0;
+  if (j < 0 && (p.stencil & (kStencilHold | kStencilCut))) j = 0;
   if (j < 0 || j > p.nt - 1) {
     out[0] = out[1] = out[2] = out[3] = 0.0;
     return;
@@ -322,6 +322,23 @@ __device__ __forceinline__ void put_cubic(float4* lds, int PU, int idx, const D4
     l2[2 * i * PU + idx] = make_double2(cx[i], cy[i]);
     l2[(2 * i + 1) * PU + idx] = make_double2(cz[i], cw[i]);
   }
+}
+
+// An all-zero entry (every plane): slices before the start of a history
+// that begins at its oldest slice.
+__device__ __forceinline__ void zero_entry(float4* lds, int PU, int idx, float) {
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  lds[idx] = z;
+  lds[PU + idx] = z;
+  lds[2 * PU + idx] = z;
+  lds[3 * PU + idx] = z;
+}
+
+__device__ __forceinline__ void zero_entry(float4* lds, int PU, int idx, double) {
+  double2* l2 = (double2*)lds;
+  const double2 z = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) l2[q * PU + idx] = z;
 }
 
 // Source values (rho, Jx, Jy, Jz) and their time derivatives at fraction f
@@ -562,6 +579,10 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
         const int k = ti.x + cs + kk;
         if (k > ti.y) continue;
         const int e = (j * kBrickCells + c) * kWmax + kk;
+        if (k < 0 && (p.stencil & kStencilCut)) {  // before the start of the history
+          zero_entry(lds, PU, e, T(0));
+          continue;
+        }
         typename RawOf<T>::type hm, h0, h1;
         load_raw(ring, p, k - 1, ti.w, c, hm);
         load_raw(ring, p, k, ti.w, c, h0);
@@ -1007,7 +1028,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       sl -= sl >= p.capacity ? p.capacity : 0;
       const unsigned cell_off = ((unsigned)ti.w * kBrickCells + (unsigned)sc) * (4u * (unsigned)sizeof(T));
       unsigned off = (unsigned)sl * sb + cell_off;
-      if (p.stencil & kStencilHold) {
+      if (p.stencil & (kStencilHold | kStencilCut)) {
         // slices before 0 read slice 0 (slot_base)
         const int o0 = (int)((unsigned)p.slot_base * sb + cell_off);
 #pragma unroll
@@ -1037,7 +1058,17 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         load_raw(ring, p, k0 - (CUB ? 2 : 1) + r, ti.w, sc, raw[r]);
     }
   };
-  auto write_round = [&](int pos, int n) {
+  // a history that starts at slice 0: the entries of earlier slices are zero
+  // (written over what the reads from the held slice 0 staged)
+  auto cut_round = [&](int pos, int n) {
+    const int4 ti = slot_entry(pos, n, sj);
+    const int k0 = ti.x + sq * EPT;
+    if ((ti.z & 1) || k0 >= 0 || !(p.stencil & kStencilCut)) return;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+      if (k0 + e < 0) zero_entry(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, T(0));
+  };
+  auto write_entries = [&](int pos, int n) {
     const int4 ti = slot_entry(pos, n, sj);
     if (ti.z & 1) return;
     if constexpr (CUB) {
@@ -1058,6 +1089,10 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     for (int e = 0; e < EPT; ++e)
       put_entry<false>(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1],
                        raw[e + 2], inv_dt);
+  };
+  auto write_round = [&](int pos, int n) {
+    write_entries(pos, n);
+    cut_round(pos, n);
   };
 
   int cursor = b_begin, tail = 0, pos = 0, cnt = 0;

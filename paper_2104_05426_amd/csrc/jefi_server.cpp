@@ -548,10 +548,12 @@ jefi_status jefi_server_create(const jefi_server_config* cfg, jefi_server** out)
   if (!cfg->arena || cfg->arena_bytes < Arena::kGranule) return JEFI_EINVAL;
   if (cfg->precision != JEFI_PREC_F64 && cfg->precision != JEFI_PREC_F32_COMP) return JEFI_EINVAL;
   const uint32_t known = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE | JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_PAST_HOLD |
-                         JEFI_FLAG_TIME_CUBIC;
+                         JEFI_FLAG_TIME_CUBIC | JEFI_FLAG_PAST_CUT;
   const uint32_t both = JEFI_FLAG_INDEX_GUARD | JEFI_FLAG_INDEX_TABLE;
   const uint32_t slope_cubic = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
-  if ((cfg->flags & ~known) != 0 || (cfg->flags & both) == both || (cfg->flags & slope_cubic) == slope_cubic)
+  const uint32_t pasts = JEFI_FLAG_PAST_HOLD | JEFI_FLAG_PAST_CUT;
+  if ((cfg->flags & ~known) != 0 || (cfg->flags & both) == both || (cfg->flags & slope_cubic) == slope_cubic ||
+      (cfg->flags & pasts) == pasts)
     return JEFI_EINVAL;
   if (cfg->reserve_cus < 0 || cfg->reserve_cus > 1024) return JEFI_EINVAL;
   if (cfg->express_cus < 0 || cfg->express_cus > 1024) return JEFI_EINVAL;

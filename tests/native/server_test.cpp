@@ -311,6 +311,8 @@ void option_flags() {
   CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
   cfg.flags = JEFI_FLAG_DERIV_SLOPE | JEFI_FLAG_TIME_CUBIC;
   CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
+  cfg.flags = JEFI_FLAG_PAST_HOLD | JEFI_FLAG_PAST_CUT;
+  CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);
   cfg.flags = 0;
   cfg.reserve_cus = -1;
   CHECK(jefi_server_create(&cfg, &bad) == JEFI_EINVAL);

@@ -56,7 +56,7 @@ def _grid(n=(4, 4, 4), h=0.1):
 @pytest.mark.parametrize("case", [
     "null-src", "bad-spacing", "nt-zero", "nt-over-capacity", "nt-over-pushed", "t-after-newest",
     "dtype-mismatch", "bad-c", "negative-screen", "null-out", "bad-dt", "bad-flags", "both-flags",
-    "slope-and-cubic", "bad-tile", "bad-reserve",
+    "slope-and-cubic", "hold-and-cut", "bad-tile", "bad-reserve",
 ])
 def test_eval_validation(case):
     """Each bad input returns EINVAL with a message, before any device call."""
@@ -91,7 +91,9 @@ def test_eval_validation(case):
     elif case == "bad-dt":
         dt = 0.0
     elif case == "bad-flags":
-        opt.flags = 32
+        opt.flags = 64
+    elif case == "hold-and-cut":
+        opt.flags = J.JEFI_FLAG_PAST_HOLD | J.JEFI_FLAG_PAST_CUT
     elif case == "slope-and-cubic":
         opt.flags = J.JEFI_FLAG_DERIV_SLOPE | J.JEFI_FLAG_TIME_CUBIC
     elif case == "both-flags":

@@ -17,7 +17,10 @@ as max |(dEx, dEy)| / max |(Ex, Ey)| (the paper's norms).
   quadrature (tests/continuum.py): the discretised sums converge to the
   reading that keeps the switch-on shell; the reading without it (the
   Coulomb and Biot-Savart fields of the box within distance t) has the
-  paper's field scale (peak 0.529 at t = 2.5) and is far from the sums."""
+  paper's field scale (peak 0.529 at t = 2.5) and is far from the sums.
+- The library's history-start reading (JEFI_FLAG_PAST_CUT: the sources
+  begin at the oldest slice, no derivative across the start) converges to
+  the shell-less continuum, within 1 % at 15^3 like the paper's figure."""
 import numpy as np
 import pytest
 
@@ -124,3 +127,21 @@ def test_paper_snapshots_against_the_continuum():
     # field (t - h)^2 / (4 t) at h = 0.2 from a face
     E0 = switched_on_box_plane(pts, 2.5, (-3.0,) * 3, (3.0,) * 3)["no_shell"][0]
     assert abs(np.sqrt(E0[0] ** 2 + E0[1] ** 2).max() - 2.3 ** 2 / 10.0) < 1e-9
+
+
+def test_history_start_reading_matches_the_shell_less_continuum():
+    torch, J = _gpu()
+    import bench
+    times = (2.5, 5.0, 7.5)
+    pts = workloads.cell_centres(_plane())
+    f = {r: bench.accuracy_fields("constant", r, times, 0.0, "f64", J.JEFI_FLAG_PAST_CUT) for r in (1, 2, 4)}
+    f32 = bench.accuracy_fields("constant", 1, times, 0.0, "f32", J.JEFI_FLAG_PAST_CUT)
+    for t in times:
+        ref = switched_on_box_plane(pts, t, (-3.0,) * 3, (3.0,) * 3)["no_shell"]
+        dev = {r: [_xoy_dev(f[r][t][i], ref[i]) for i in (0, 1)] for r in f}
+        print(f"constant sources t = {t}, history start: " +
+              ", ".join(f"{15 * r}^3 {d[0]:.3%} (E) {d[1]:.3%} (B)" for r, d in dev.items()), flush=True)
+        assert max(dev[1]) < 0.01, (t, dev)
+        assert dev[4][0] < dev[1][0] and dev[4][1] < dev[1][1], (t, dev)
+        d32 = [_xoy_dev(f32[t][i], ref[i]) for i in (0, 1)]
+        assert abs(d32[0] - dev[1][0]) < 1e-4 and abs(d32[1] - dev[1][1]) < 1e-4, (t, d32, dev[1])

@@ -17,11 +17,12 @@ pytestmark = pytest.mark.gpu
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 
-# oracle stencil bits: 1 slope, 2 hold, 4 cubic (slope and cubic exclude each other)
-READINGS = (0, 1, 2, 3, 4, 6)
+# oracle stencil bits: 1 slope, 2 hold, 4 cubic, 8 history start (slope and cubic,
+# hold and history start exclude each other)
+READINGS = (0, 1, 2, 3, 4, 6, 8, 9, 12)
 
 
-@pytest.mark.parametrize("seed", range(36))
+@pytest.mark.parametrize("seed", range(6 * len(READINGS)))
 def test_random_option_combinations(seed):
     import torch
     if not torch.cuda.is_available():
@@ -34,8 +35,8 @@ def test_random_option_combinations(seed):
         p = Problem(p.name + "-early", p.src, p.obs, p.hist, p.dt, t_old - float(rng.uniform(0.2, 4.0)) * p.dt,
                     p.t0, p.newest, p.c, p.screen)
     idx = seed % 3                               # auto, guard, table
-    stencil = READINGS[(seed // 3) % 6]          # each (index mode, reading) pair twice
-    flags = idx | (stencil << 2)                 # JEFI_FLAG_DERIV_SLOPE = 4, _PAST_HOLD = 8, _TIME_CUBIC = 16
+    stencil = READINGS[(seed // 3) % len(READINGS)]  # each (index mode, reading) pair twice
+    flags = idx | (stencil << 2)  # JEFI_FLAG_DERIV_SLOPE = 4, _PAST_HOLD = 8, _TIME_CUBIC = 16, _PAST_CUT = 32
     tile = int(rng.integers(0, 3))
     Er, Br = oracle.eval_problem(p, stencil=stencil)
     fp_ref = oracle.slice_fingerprint(p.src, p.obs, p.nt, p.dt, p.t, p.t0, p.newest, p.c, p.screen)

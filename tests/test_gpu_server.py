@@ -129,8 +129,8 @@ def _check_solo(J, reqs, full, n_oracle=4, prec="f32", flags=0):
         if i < n_oracle:
             p = Problem("srv", s["src"], r["obs"], window, s["dt"], t, 0.0, r["newest"], 1.0,
                         workloads.default_screen(s["src"]))
-            # library stencil flags 4, 8, 16 -> oracle stencil bits 1, 2, 4
-            Er, Br = oracle.eval_problem(p, stencil=(flags >> 2) & 7)
+            # library stencil flags 4, 8, 16, 32 -> oracle stencil bits 1, 2, 4, 8
+            Er, Br = oracle.eval_problem(p, stencil=(flags >> 2) & 15)
             check_fields(r["E"], r["B"], Er, Br, ORACLE_TOL[prec], f"served #{i} vs oracle")
 
 
@@ -194,15 +194,20 @@ def test_server_express_lane(prec):
     _check_solo(J, reqs, full, n_oracle=3, prec=prec)
 
 
-@pytest.mark.parametrize("prec,reading", [("f32", "slope"), ("f64", "slope"), ("f32", "cubic"), ("f64", "cubic")])
+@pytest.mark.parametrize("prec,reading", [("f32", "slope"), ("f64", "slope"), ("f32", "cubic"), ("f64", "cubic"),
+                                          ("f32", "cut"), ("f64", "cut")])
 def test_server_with_stencil_flags(prec, reading):
     """A server whose evaluations use alternative stencil readings (slope
-    derivative or cubic interpolation, with the held past) and the table
-    index mode: every result equals the same evaluation alone with those
-    flags, and the oracle with those readings."""
+    derivative or cubic interpolation, with the held past; or the history
+    starting at the oldest slice) and the table index mode: every result
+    equals the same evaluation alone with those flags, and the oracle with
+    those readings."""
     J = _gpu()
-    flags = (J.JEFI_FLAG_DERIV_SLOPE if reading == "slope" else J.JEFI_FLAG_TIME_CUBIC) | J.JEFI_FLAG_PAST_HOLD | \
-        (J.JEFI_FLAG_INDEX_TABLE if prec == "f32" else 0)
+    if reading == "cut":
+        flags = J.JEFI_FLAG_PAST_CUT
+    else:
+        flags = (J.JEFI_FLAG_DERIV_SLOPE if reading == "slope" else J.JEFI_FLAG_TIME_CUBIC) | J.JEFI_FLAG_PAST_HOLD
+    flags |= J.JEFI_FLAG_INDEX_TABLE if prec == "f32" else 0
     reqs, results, stats, full = _run_stream(J, 1 << 30, n_sessions=4, n_req=20, seed=12, prec=prec, flags=flags)
     assert stats["completed"] == 20 and stats["failed"] == 0
     _check_solo(J, reqs, full, n_oracle=3, prec=prec, flags=flags)

@@ -24,7 +24,9 @@ SOLO = {"f64": 1e-13, "f32": 2e-6}
 # library flag -> oracle stencil bits
 VARIANTS = {"slope": (4, oracle.STENCIL_SLOPE), "hold": (8, oracle.STENCIL_HOLD),
             "both": (12, oracle.STENCIL_SLOPE | oracle.STENCIL_HOLD),
-            "cubic": (16, oracle.STENCIL_CUBIC), "cubic+hold": (24, oracle.STENCIL_CUBIC | oracle.STENCIL_HOLD)}
+            "cubic": (16, oracle.STENCIL_CUBIC), "cubic+hold": (24, oracle.STENCIL_CUBIC | oracle.STENCIL_HOLD),
+            "cut": (32, oracle.STENCIL_CUT), "slope+cut": (36, oracle.STENCIL_SLOPE | oracle.STENCIL_CUT),
+            "cubic+cut": (48, oracle.STENCIL_CUBIC | oracle.STENCIL_CUT)}
 
 
 def _gpu():
@@ -79,7 +81,27 @@ def test_times_before_the_window(variant):
             assert np.all(Ez == 0.0) and np.all(Bz == 0.0)
 
 
-@pytest.mark.parametrize("ratio,variant", [(r, v) for r in (4, 8, 10) for v in ("both", "cubic+hold", "cubic")])
+@pytest.mark.parametrize("variant", ["cut", "slope+cut", "cubic+cut"])
+def test_history_start_around_the_window(variant):
+    """A history that starts at the oldest slice: evaluation times before it
+    give exact zeros (every retarded time precedes the start), times just
+    after it and later match the oracle with the same reading."""
+    G = _gpu()
+    flag, st = VARIANTS[variant]
+    base = _ragged_problem(4)
+    t_old = base.t0 + (base.newest - base.nt + 1) * base.dt
+    for off in (-40.0, -0.6, 0.3, 2.7):
+        p = _retimed(base, t_old + off * base.dt, f"start{off}")
+        Er, Br = oracle.eval_problem(p, stencil=st)
+        for prec in ["f64", "f32"]:
+            Eg, Bg = G.gpu_eval(p, prec, flags=flag)
+            if off < 0.0:
+                assert np.all(Er == 0.0) and np.all(Eg == 0.0) and np.all(Bg == 0.0), (off, prec)
+            else:
+                _assert_fields(Eg, Bg, Er, Br, TOL[prec], f"t_old{off:+}dt {variant} {prec}")
+
+
+@pytest.mark.parametrize("ratio,variant", [(r, v) for r in (4, 8, 10) for v in ("both", "cubic+hold", "cubic", "cut")])
 def test_staging_window_sizes(ratio, variant):
     """Readings on the 64- and 128-slot staging shapes and the chunked
     kernel (spacing / (c dt) = 4, 8, 10), with a window shorter than the
