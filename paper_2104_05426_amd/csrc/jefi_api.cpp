@@ -665,7 +665,7 @@ int launch_cus(int reserve) {
 // persistent pair launch per non-empty group -> split reduction.  Its
 // arguments are workspace pointers only (counts live in device memory), so
 // it replays any batch that fits the workspace.
-jefi_status build_graph(BatchWorkspace& w, int is_f64, const bool has[2], int idx, int cub, int cus,
+jefi_status build_graph(BatchWorkspace& w, int is_f64, const bool has[2], int idx, int stg, int cus,
                         hipGraphExec_t* out) {
   hipGraph_t g;
   hipError_t e = hipGraphCreate(&g, 0);
@@ -696,7 +696,7 @@ jefi_status build_graph(BatchWorkspace& w, int is_f64, const bool has[2], int id
     if (!has[q]) continue;
     hipGraphNode_t np;
     kp.kernelParams = q == 0 ? args0 : args1;
-    kp.func = batch_pair_kernel(is_f64, kGroupWz[q], idx, cub);
+    kp.func = batch_pair_kernel(is_f64, kGroupWz[q], idx, stg);
     kp.gridDim = dim3(cus * slots_per_cu(kGroupWz[q]));
     kp.blockDim = dim3(batch_pair_threads(kGroupWz[q]));
     e = hipGraphAddKernelNode(&np, g, &prev, 1, &kp);
@@ -1226,12 +1226,13 @@ jefi_status eval_batch_impl(const jefi_problem* probs, int32_t n, const jefi_opt
     w.bd = bd;
   }
   // one stencil for the whole batch (the options are shared)
-  const int cub = nb > 0 && (params[0].stencil & kStencilCubic) ? 1 : 0;
-  const long long gkey = (long long)run_cus * 64 + cub * 16 + is_f64 * 8 + idx * 4 + (has[0] ? 2 : 0) + (has[1] ? 1 : 0);
+  // staging mode of the persistent kernels: bit 0 cubic, bit 1 history start (one per batch)
+  const int stg = nb > 0 ? ((params[0].stencil & kStencilCubic) ? 1 : 0) | ((params[0].stencil & kStencilCut) ? 2 : 0) : 0;
+  const long long gkey = (long long)run_cus * 64 + stg * 16 + is_f64 * 8 + idx * 4 + (has[0] ? 2 : 0) + (has[1] ? 1 : 0);
   auto it = w.graphs.find(gkey);
   if (it == w.graphs.end()) {
     hipGraphExec_t ge;
-    jefi_status st = build_graph(w, is_f64, has, idx, cub, run_cus, &ge);
+    jefi_status st = build_graph(w, is_f64, has, idx, stg, run_cus, &ge);
     if (st != JEFI_OK) return st;
     it = w.graphs.emplace(gkey, ge).first;
   }

@@ -134,7 +134,7 @@ void* batch_reset_kernel();
 void* batch_threshold_kernel();
 // idx: index mode of the FP32 kernel (1 = threshold table for every pair,
 // needs use_thr in every instance; 0 = guard band).
-void* batch_pair_kernel(int is_f64, int wz, int idx, int cubic);
+void* batch_pair_kernel(int is_f64, int wz, int idx, int stg);  // stg: bit 0 cubic, bit 1 history start
 void* batch_epilogue_kernel();
 int batch_pair_threads(int wz);
 hipError_t launch_epilogue(const EpilogueParams& p, hipStream_t s);

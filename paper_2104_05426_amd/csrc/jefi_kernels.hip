@@ -233,7 +233,7 @@ struct RawOf<double> {
 // interpolant (SLOPE): D = (h_(k+1) - h_k)/dt, T = 0.
 template <bool SLOPE>
 __device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const float4& hm, const float4& h0,
-                                          const float4& h1, float inv_dt) {
+                                          const float4& h1, float inv_dt, bool value = true) {
   float4 S, D, Tn;
   S.x = h1.x - h0.x; S.y = h1.y - h0.y; S.z = h1.z - h0.z; S.w = h1.w - h0.w;
   if (SLOPE) {
@@ -245,7 +245,7 @@ __device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const fl
     Tn.x = S.x * inv_dt - D.x; Tn.y = S.y * inv_dt - D.y;
     Tn.z = S.z * inv_dt - D.z; Tn.w = S.w * inv_dt - D.w;
   }
-  lds[idx] = h0;
+  lds[idx] = value ? h0 : make_float4(0.f, 0.f, 0.f, 0.f);
   lds[PU + idx] = S;
   lds[2 * PU + idx] = D;
   lds[3 * PU + idx] = Tn;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const fl
 
 template <bool SLOPE>
 __device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const D4& hm, const D4& h0,
-                                          const D4& h1, double inv_dt) {
+                                          const D4& h1, double inv_dt, bool value = true) {
   const double a[4] = {hm.x, hm.y, hm.z, hm.w};
   const double b[4] = {h0.x, h0.y, h0.z, h0.w};
   const double c[4] = {h1.x, h1.y, h1.z, h1.w};
@@ -269,8 +269,8 @@ __device__ __forceinline__ void put_entry(float4* lds, int PU, int idx, const D4
     }
   }
   double2* l2 = (double2*)lds;
-  l2[idx] = make_double2(b[0], b[1]);
-  l2[PU + idx] = make_double2(b[2], b[3]);
+  l2[idx] = value ? make_double2(b[0], b[1]) : make_double2(0.0, 0.0);
+  l2[PU + idx] = value ? make_double2(b[2], b[3]) : make_double2(0.0, 0.0);
   l2[2 * PU + idx] = make_double2(S[0], S[1]);
   l2[3 * PU + idx] = make_double2(S[2], S[3]);
   l2[4 * PU + idx] = make_double2(D[0], D[1]);
@@ -301,22 +301,24 @@ __device__ __forceinline__ void cubic_coef(double h2, double h1, double h0, doub
 }
 
 __device__ __forceinline__ void put_cubic(float4* lds, int PU, int idx, const float4& h2, const float4& h1,
-                                          const float4& h0, const float4& hp) {
+                                          const float4& h0, const float4& hp, bool value = true) {
   float cx[4], cy[4], cz[4], cw[4];
   cubic_coef(h2.x, h1.x, h0.x, hp.x, cx);
   cubic_coef(h2.y, h1.y, h0.y, hp.y, cy);
   cubic_coef(h2.z, h1.z, h0.z, hp.z, cz);
   cubic_coef(h2.w, h1.w, h0.w, hp.w, cw);
+  if (!value) cx[0] = cy[0] = cz[0] = cw[0] = 0.f;
   for (int i = 0; i < 4; ++i) lds[i * PU + idx] = make_float4(cx[i], cy[i], cz[i], cw[i]);
 }
 
 __device__ __forceinline__ void put_cubic(float4* lds, int PU, int idx, const D4& h2, const D4& h1, const D4& h0,
-                                          const D4& hp) {
+                                          const D4& hp, bool value = true) {
   double cx[4], cy[4], cz[4], cw[4];
   cubic_coef(h2.x, h1.x, h0.x, hp.x, cx);
   cubic_coef(h2.y, h1.y, h0.y, hp.y, cy);
   cubic_coef(h2.z, h1.z, h0.z, hp.z, cz);
   cubic_coef(h2.w, h1.w, h0.w, hp.w, cw);
+  if (!value) cx[0] = cy[0] = cz[0] = cw[0] = 0.0;
   double2* l2 = (double2*)lds;
   for (int i = 0; i < 4; ++i) {
     l2[2 * i * PU + idx] = make_double2(cx[i], cy[i]);
@@ -324,22 +326,6 @@ __device__ __forceinline__ void put_cubic(float4* lds, int PU, int idx, const D4
   }
 }
 
-// An all-zero entry (every plane): slices before the start of a history
-// that begins at its oldest slice.
-__device__ __forceinline__ void zero_entry(float4* lds, int PU, int idx, float) {
-  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-  lds[idx] = z;
-  lds[PU + idx] = z;
-  lds[2 * PU + idx] = z;
-  lds[3 * PU + idx] = z;
-}
-
-__device__ __forceinline__ void zero_entry(float4* lds, int PU, int idx, double) {
-  double2* l2 = (double2*)lds;
-  const double2 z = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) l2[q * PU + idx] = z;
-}
 
 // Source values (rho, Jx, Jy, Jz) and their time derivatives at fraction f
 // of LDS entry e.  Linear planes (h, S, D, T): value h + f S, derivative
@@ -579,22 +565,21 @@ __global__ __launch_bounds__(kThreads) void pair_kernel(PairParams p) {
         const int k = ti.x + cs + kk;
         if (k > ti.y) continue;
         const int e = (j * kBrickCells + c) * kWmax + kk;
-        if (k < 0 && (p.stencil & kStencilCut)) {  // before the start of the history
-          zero_entry(lds, PU, e, T(0));
-          continue;
-        }
         typename RawOf<T>::type hm, h0, h1;
         load_raw(ring, p, k - 1, ti.w, c, hm);
         load_raw(ring, p, k, ti.w, c, h0);
         load_raw(ring, p, k + 1, ti.w, c, h1);
+        // a history that starts at slice 0 keeps no value before it (the
+        // held reads make every other plane zero there)
+        const bool value = k >= 0 || !(p.stencil & kStencilCut);
         if (p.stencil & kStencilCubic) {
           typename RawOf<T>::type h2;
           load_raw(ring, p, k - 2, ti.w, c, h2);
-          put_cubic(lds, PU, e, h2, hm, h0, h1);
+          put_cubic(lds, PU, e, h2, hm, h0, h1, value);
         } else if (p.stencil & kStencilSlope)
-          put_entry<true>(lds, PU, e, hm, h0, h1, inv_dt);
+          put_entry<true>(lds, PU, e, hm, h0, h1, inv_dt, value);
         else
-          put_entry<false>(lds, PU, e, hm, h0, h1, inv_dt);
+          put_entry<false>(lds, PU, e, hm, h0, h1, inv_dt, value);
       }
       __syncthreads();
 
@@ -913,14 +898,18 @@ struct FastShape {
 // IDX (FP32 only): 0 = FP32 index with guard band and FP64 re-decision,
 // 1 = threshold-table decision for every pair of a full brick.  PP is
 // PairParams as a kernel argument, or in the constant address space for
-// the persistent kernel (uniform, read-only: scalar loads).
-template <typename T, int WZ, bool FP, int IDX, int W, bool CUB, class PP>
+// the persistent kernel (uniform, read-only: scalar loads).  STG: staging
+// mode, bit 0 = cubic planes, bit 1 = a history that starts at slice 0 (its
+// own instantiations, so the other kernels' code is unchanged by it).
+template <typename T, int WZ, bool FP, int IDX, int W, int STG, class PP>
 __device__ __forceinline__ void pair_body(const PP& p, int bid,
                                           float4 (&lds)[FastShape<T, WZ, W>::NPL * FastShape<T, WZ, W>::PU],
                                           int4 (&tab_i)[kBrickRing], float4 (&tab_f)[kBrickRing],
                                           double (&tab_c)[kBrickRing][6],
                                           double (&thr)[FastShape<T, WZ, W>::THR], int (&qs)[2]) {
   using Raw = typename RawOf<T>::type;
+  constexpr bool CUB = (STG & 1) != 0;
+  constexpr bool PCUT = (STG & 2) != 0;
   constexpr int G = FastShape<T, WZ, W>::G;
   constexpr int kThreads = FastShape<T, WZ, W>::KT;
   constexpr int PU = FastShape<T, WZ, W>::PU;
@@ -1058,41 +1047,27 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
         load_raw(ring, p, k0 - (CUB ? 2 : 1) + r, ti.w, sc, raw[r]);
     }
   };
-  // a history that starts at slice 0: the entries of earlier slices are zero
-  // (written over what the reads from the held slice 0 staged)
-  auto cut_round = [&](int pos, int n) {
-    const int4 ti = slot_entry(pos, n, sj);
-    const int k0 = ti.x + sq * EPT;
-    if ((ti.z & 1) || k0 >= 0 || !(p.stencil & kStencilCut)) return;
-#pragma unroll
-    for (int e = 0; e < EPT; ++e)
-      if (k0 + e < 0) zero_entry(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, T(0));
-  };
-  auto write_entries = [&](int pos, int n) {
+  auto write_round = [&](int pos, int n) {
     const int4 ti = slot_entry(pos, n, sj);
     if (ti.z & 1) return;
+    const int base = (sj * kBrickCells + sc) * kCellStride + sq * EPT;
+    // A history that starts at slice 0: an entry of an earlier slice was
+    // staged from the held slice 0 at every node, so all its planes but the
+    // value are zero already; it keeps no value either.
+    const int kv = PCUT ? -(ti.x + sq * EPT) : INT_MIN;  // entries e < kv lie before
     if constexpr (CUB) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e)
-        put_cubic(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1], raw[e + 2],
-                  raw[e + 3]);
-      return;
-    }
-    if (p.stencil & kStencilSlope) {
+        put_cubic(lds, PU, base + e, raw[e], raw[e + 1], raw[e + 2], raw[e + 3], e >= kv);
+    } else if (p.stencil & kStencilSlope) {
 #pragma unroll
       for (int e = 0; e < EPT; ++e)
-        put_entry<true>(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1],
-                        raw[e + 2], inv_dt);
-      return;
-    }
+        put_entry<true>(lds, PU, base + e, raw[e], raw[e + 1], raw[e + 2], inv_dt, e >= kv);
+    } else {
 #pragma unroll
-    for (int e = 0; e < EPT; ++e)
-      put_entry<false>(lds, PU, (sj * kBrickCells + sc) * kCellStride + sq * EPT + e, raw[e], raw[e + 1],
-                       raw[e + 2], inv_dt);
-  };
-  auto write_round = [&](int pos, int n) {
-    write_entries(pos, n);
-    cut_round(pos, n);
+      for (int e = 0; e < EPT; ++e)
+        put_entry<false>(lds, PU, base + e, raw[e], raw[e + 1], raw[e + 2], inv_dt, e >= kv);
+    }
   };
 
   int cursor = b_begin, tail = 0, pos = 0, cnt = 0;
@@ -1480,7 +1455,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   }
 }
 
-template <typename T, int WZ, bool FP, int IDX, int W, bool CUB>
+template <typename T, int WZ, bool FP, int IDX, int W, int STG>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
   using S = FastShape<T, WZ, W>;
   __shared__ float4 lds[S::NPL * S::PU];
@@ -1489,14 +1464,14 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
   __shared__ double tab_c[kBrickRing][6];
   __shared__ double thr[S::THR];
   __shared__ int qs[2];
-  pair_body<T, WZ, FP, IDX, W, CUB>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab_i, tab_f,
+  pair_body<T, WZ, FP, IDX, W, STG>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab_i, tab_f,
                                     tab_c, thr, qs);
 }
 
 // Persistent batched launch: workgroups pull (instance, workgroup id) items
 // from a queue ordered heaviest first until it is empty.  IDX as for
 // pair_body, one value for the whole batch.
-template <typename T, int WZ, int IDX, bool CUB>
+template <typename T, int WZ, int IDX, int STG>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_persistent(BatchDevice bd) {
   using S = FastShape<T, WZ, 32>;
   __shared__ float4 lds[S::NPL * S::PU];
@@ -1519,7 +1494,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
     using CP = const __attribute__((address_space(4))) PairParams;
     CP& p = *(CP*)(bd.params + inst);
-    pair_body<T, WZ, false, IDX, 32, CUB>(p, bid, lds, tab_i, tab_f, tab_c, thr, qs);
+    pair_body<T, WZ, false, IDX, 32, STG>(p, bid, lds, tab_i, tab_f, tab_c, thr, qs);
   }
 }
 
@@ -1765,18 +1740,23 @@ hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, i
 hipError_t launch_pairs(const PairParams& p, int is_f64, int fingerprint, int multi_chunk, int wsel,
                         hipStream_t s) {
   dim3 grid(p.n_wg), block(kThreads);
-  // the fingerprint pass takes slice decisions only: no cubic variant
+  // the fingerprint pass takes slice decisions only: no staging variants
   const bool cub = !fingerprint && (p.stencil & kStencilCubic) != 0;
+  const bool cut = !fingerprint && (p.stencil & kStencilCut) != 0;
 #define JEFI_LAUNCH(T, G, FPM, MUL) \
   hipLaunchKernelGGL((pair_kernel<T, G, FPM, MUL>), grid, block, 0, s, p)
 #define JEFI_FAST(T, WZ, FPM, IDX, W)                                                                    \
   do {                                                                                                  \
     if (FPM)                                                                                            \
-      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, true, IDX, W, false>), grid, dim3(256 * WZ), 0, s, p); \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, true, IDX, W, 0>), grid, dim3(256 * WZ), 0, s, p);    \
+    else if (cub && cut)                                                                                \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, 3>), grid, dim3(256 * WZ), 0, s, p);   \
     else if (cub)                                                                                       \
-      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, true>), grid, dim3(256 * WZ), 0, s, p); \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, 1>), grid, dim3(256 * WZ), 0, s, p);   \
+    else if (cut)                                                                                       \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, 2>), grid, dim3(256 * WZ), 0, s, p);   \
     else                                                                                                \
-      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, false>), grid, dim3(256 * WZ), 0, s, p); \
+      hipLaunchKernelGGL((pair_kernel_fast<T, WZ, false, IDX, W, 0>), grid, dim3(256 * WZ), 0, s, p);   \
   } while (0)
 #define JEFI_FAST_F32(WZ, FPM, W)        \
   do {                                  \
@@ -1839,19 +1819,22 @@ hipError_t launch_thresholds(double* out, int lo, int n, double af, double icdt,
 void* batch_reset_kernel() { return (void*)batch_reset; }
 void* batch_threshold_kernel() { return (void*)batch_threshold; }
 void* batch_epilogue_kernel() { return (void*)batch_epilogue; }
-void* batch_pair_kernel(int is_f64, int wz, int idx, int cubic) {
-  if (cubic) {
-    if (is_f64)
-      return wz == 2 ? (void*)pair_kernel_persistent<double, 2, 0, true> : (void*)pair_kernel_persistent<double, 1, 0, true>;
-    if (idx)
-      return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 1, true> : (void*)pair_kernel_persistent<float, 1, 1, true>;
-    return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 0, true> : (void*)pair_kernel_persistent<float, 1, 0, true>;
-  }
+template <int STG>
+static void* batch_pair_kernel_stg(int is_f64, int wz, int idx) {
   if (is_f64)
-    return wz == 2 ? (void*)pair_kernel_persistent<double, 2, 0, false> : (void*)pair_kernel_persistent<double, 1, 0, false>;
+    return wz == 2 ? (void*)pair_kernel_persistent<double, 2, 0, STG> : (void*)pair_kernel_persistent<double, 1, 0, STG>;
   if (idx)
-    return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 1, false> : (void*)pair_kernel_persistent<float, 1, 1, false>;
-  return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 0, false> : (void*)pair_kernel_persistent<float, 1, 0, false>;
+    return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 1, STG> : (void*)pair_kernel_persistent<float, 1, 1, STG>;
+  return wz == 2 ? (void*)pair_kernel_persistent<float, 2, 0, STG> : (void*)pair_kernel_persistent<float, 1, 0, STG>;
+}
+
+void* batch_pair_kernel(int is_f64, int wz, int idx, int stg) {
+  switch (stg) {
+    case 1: return batch_pair_kernel_stg<1>(is_f64, wz, idx);
+    case 2: return batch_pair_kernel_stg<2>(is_f64, wz, idx);
+    case 3: return batch_pair_kernel_stg<3>(is_f64, wz, idx);
+    default: return batch_pair_kernel_stg<0>(is_f64, wz, idx);
+  }
 }
 int batch_pair_threads(int wz) { return 256 * wz; }
 
