@@ -214,3 +214,39 @@ def test_autotune_batch_equals_solo_and_oracle(prec):
     solo = run.run_solo(0)
     _check_against(batch, solo, SOLO[prec], f"tuned batch vs solo {prec}")
     _against_oracle(batch, probs, prec, f"tuned batch vs oracle {prec}")
+
+
+def test_full_size_batch_of_the_benchmark():
+    """The 64-instance batch at the benchmark's own sizes (source edges
+    8..40, observation edges 8..48, histories 2 e_s + 8; 4.4e10 pairs): the
+    batched FP32 and FP64 results against the per-instance FP64 path on every
+    point, and against the oracle on sampled points of every instance."""
+    J, torch = _gpu()
+    probs = workloads.batch_instances(64, seed=3)
+    outs = {}
+    for prec, batched in (("f64", False), ("f64", True), ("f32", True)):
+        hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP)
+        rings = [J.upload_history(p.src, p.hist, hdt, t0=p.t0, newest=p.newest, capacity=p.nt) for p in probs]
+        res = [(torch.empty((3, p.obs.size), dtype=tdt, device="cuda"),
+                torch.empty((3, p.obs.size), dtype=tdt, device="cuda")) for p in probs]
+        if batched:
+            J.jefi_eval_batch([J.make_problem(p.src, h, p.dt, p.nt, p.obs, p.t, E, B)
+                               for (st, h), p, (E, B) in zip(rings, probs, res)], opt)
+        else:
+            for (st, h), p, (E, B) in zip(rings, probs, res):
+                J.jefi_eval_fields(p.src, h, p.dt, p.nt, p.obs, p.t, E, B, opt)
+        torch.cuda.synchronize()
+        outs[prec, batched] = [(E.double().cpu().numpy(), B.double().cpu().numpy()) for E, B in res]
+        del rings, res
+        torch.cuda.empty_cache()
+    ref = outs["f64", False]
+    for key, tol in ((("f64", True), 1e-12), (("f32", True), 1e-5)):
+        for i, ((E, B), (Er, Br)) in enumerate(zip(outs[key], ref)):
+            check_fields(E, B, Er, Br, tol, "" if i else f"full batch {key[0]} vs FP64 path")
+    rng = np.random.default_rng(17)
+    for i, p in enumerate(probs):
+        sel = np.sort(rng.choice(p.obs.size, size=min(4, p.obs.size), replace=False))
+        Er, Br = oracle.eval_problem(p, sel=sel)
+        check_fields(ref[i][0][:, sel], ref[i][1][:, sel], Er, Br, 1e-12, "" if i else "FP64 path vs oracle")
