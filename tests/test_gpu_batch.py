@@ -221,7 +221,9 @@ def test_full_size_batch_of_the_benchmark():
     8..40, observation edges 8..48, histories 2 e_s + 8; 4.4e10 pairs): the
     batched FP32 and FP64 results against the per-instance FP64 path on every
     point, and against the oracle on sampled points of every instance."""
-    J, torch = _gpu()
+    _gpu()
+    import torch
+    import paper_2104_05426_amd as J
     probs = workloads.batch_instances(64, seed=3)
     outs = {}
     for prec, batched in (("f64", False), ("f64", True), ("f32", True)):
