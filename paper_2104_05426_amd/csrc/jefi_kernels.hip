@@ -1351,20 +1351,33 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           }
           const double exy[4] = {x2[0] + y2[0], x2[1] + y2[0], x2[0] + y2[1], x2[1] + y2[1]};
           const int s_base = FP ? brick_s_base(ti.w) : 0;
+          // one z layer (four cells) at a time: the four index decisions, whose
+          // threshold reads are then in flight together, before the four
+          // field contributions
 #pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const double r2 = exy[c & 3] + z2[c >> 2];  // (dx*dx + dy*dy) + dz*dz
-            const double ri = rsqrt_f64(r2);
-            const double u = __builtin_fma(-(r2 * ri), p.inv_cdt, p.a_f);
-            const int nn = (int)__builtin_rint(u);
-            const int mm = r2 <= thr_at[nn] ? nn : nn - 1;
-            if (FP) {
-              fpa.add(p.a_i + mm, cell_s(s_base, c));
-              continue;
+          for (int cz = 0; cz < 2; ++cz) {
+            double r2[4], ri[4], u[4], tn[4];
+            int nn[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              r2[q] = exy[q] + z2[cz];  // (dx*dx + dy*dy) + dz*dz
+              ri[q] = rsqrt_f64(r2[q]);
+              u[q] = __builtin_fma(-(r2[q] * ri[q]), p.inv_cdt, p.a_f);
+              nn[q] = (int)__builtin_rint(u[q]);
             }
-            const int e = cellbase + c * kCellStride + max(mm, mlo);
-            pair_fields<CUB>(lds, PU, e, u - (double)mm, ri, ex[c & 1], ey[(c >> 1) & 1], ez[c >> 2], dE, dB,
-                             inv_dt);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tn[q] = thr_at[nn[q]];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int c = 4 * cz + q;
+              const int mm = r2[q] <= tn[q] ? nn[q] : nn[q] - 1;
+              if (FP) {
+                fpa.add(p.a_i + mm, cell_s(s_base, c));
+                continue;
+              }
+              const int e = cellbase + c * kCellStride + max(mm, mlo);
+              pair_fields<CUB>(lds, PU, e, u[q] - (double)mm, ri[q], ex[q & 1], ey[q >> 1], ez[cz], dE, dB, inv_dt);
+            }
           }
           continue;
         }
