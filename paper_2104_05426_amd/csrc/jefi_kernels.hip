@@ -910,12 +910,6 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   using Raw = typename RawOf<T>::type;
   constexpr bool CUB = (STG & 1) != 0;
   constexpr bool PCUT = (STG & 2) != 0;
-  // FP32: the next round's raw slices are loaded into registers while the
-  // current round computes.  FP64 loads them at the top of the round: its
-  // registers are better spent on the pair loop (the batched FP64 kernel
-  // spills 14 registers instead of 91, 5 % faster; the single launch is
-  // unchanged).
-  constexpr bool PREFETCH = sizeof(T) == 4;
   constexpr int G = FastShape<T, WZ, W>::G;
   constexpr int kThreads = FastShape<T, WZ, W>::KT;
   constexpr int PU = FastShape<T, WZ, W>::PU;
@@ -1083,7 +1077,6 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     tail = __builtin_amdgcn_readfirstlane(qs[0]);  // uniform: keeps ring positions scalar
     cursor = __builtin_amdgcn_readfirstlane(qs[1]);
     cnt = min(G, tail);
-    if (PREFETCH) load_round(0, cnt);
   }
   // Source-cell index of a brick's first cell (fingerprints only).
   auto brick_s_base = [&](int b) {
@@ -1109,7 +1102,10 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   float sy0 = 0.f, sy1 = 0.f, sz0 = 0.f, sz1 = 0.f, yzs[4] = {0.f, 0.f, 0.f, 0.f};
   double ey2s[2] = {0.0, 0.0}, ez2s[2] = {0.0, 0.0};
   for (bool more = b_begin < b_end; more;) {
-    if (!PREFETCH) load_round(pos, cnt);
+    // each round loads its raw slices at its start: holding the next round's
+    // in registers while this one computes costs the pair loop more (spills)
+    // than the loads' latency
+    load_round(pos, cnt);
     write_round(pos, cnt);
     const int npos = pos + cnt;
     const bool probe = tail - npos < G && cursor < b_end;
@@ -1121,7 +1117,6 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     }
     const int ncnt = min(G, tail - npos);
     const bool next = ncnt > 0 || cursor < b_end;
-    if (PREFETCH && ncnt > 0) load_round(npos, ncnt);
 
     // a wavefront whose 4x4x4 block lies wholly outside the observation
     // grid (tile padding) stages but computes nothing
