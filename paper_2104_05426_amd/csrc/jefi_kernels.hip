@@ -213,8 +213,19 @@ __device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, int off, D
   out = D4{lo.x, lo.y, hi.x, hi.y};
 }
 
-__device__ __forceinline__ void zero_raw(float4& v) { v = make_float4(0.f, 0.f, 0.f, 0.f); }
-__device__ __forceinline__ void zero_raw(D4& v) { v = D4{0.0, 0.0, 0.0, 0.0}; }
+// The same loads with a wavefront-uniform part of the offset in soff (a
+// scalar register) and the per-lane part in voff.
+__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, float4& out) {
+  const f32x4_t v = __builtin_bit_cast(f32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+  out = make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void buffer_raw(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff, D4& out) {
+  const f64x2_t lo = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+  const f64x2_t hi = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16u, soff, 0));
+  out = D4{lo.x, lo.y, hi.x, hi.y};
+}
+
 
 template <typename T>
 struct RawOf;
@@ -998,8 +1009,16 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   auto slot_entry = [&](int pos, int n, int j) {
     return j < n ? tab_i[(pos + j) & (kBrickRing - 1)] : make_int4(0, -1, 1, 0);
   };
-  auto load_round = [&](int pos, int n) {
-    const int4 ti = slot_entry(pos, n, sj);
+  // The 64 threads of a wavefront stage one brick slot (NQ is a multiple of
+  // 8, so t >> 3 stays within one sj): the slot's table entry, its ring
+  // slots and their range tests are uniform across the wavefront.
+  static_assert(NQ % 8 == 0, "one brick slot per wavefront");
+  const int sq0 = __builtin_amdgcn_readfirstlane(sq & ~7);  // first slot group of this wavefront
+  const int sjw = __builtin_amdgcn_readfirstlane(sj);
+  // per-lane part of a ring offset on the uniform path: slot group, cell
+  const unsigned lane_off = (unsigned)((sq & 7) * EPT) * ((unsigned)p.slot_elems * (unsigned)sizeof(T)) +
+                            (unsigned)sc * (4u * (unsigned)sizeof(T));
+  auto load_round = [&](const int4& ti) {
     const int k0 = ti.x + sq * EPT;
     if (p.ring_bytes_rs != 0u) {
       // Buffer addressing over the ring: 32-bit offsets stepped slot by
@@ -1008,7 +1027,24 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       const __amdgpu_buffer_rsrc_t rs =
           __builtin_amdgcn_make_buffer_rsrc((void*)p.ring, (short)0, (int)p.ring_bytes_rs, kRawBufferFlags);
       const unsigned sb = (unsigned)p.slot_elems * (unsigned)sizeof(T);
-      const int j0 = (ti.z & 1) ? p.nt : k0 - (CUB ? 2 : 1);  // dead bricks: every load out of range
+      {
+        // This wavefront's raw slices jw .. jw + SPAN - 1: when all lie in
+        // 0..nt-1 and in consecutive ring slots, a scalar offset per slice.
+        constexpr int SPAN = 7 * EPT + NRAW;
+        const int jw = ti.x - (CUB ? 2 : 1) + sq0 * EPT;
+        int slw = p.slot_base + jw;
+        slw -= slw >= p.capacity ? p.capacity : 0;
+        if (jw >= 0 && jw + SPAN <= p.nt && slw + SPAN <= p.capacity) {
+          unsigned so = (unsigned)slw * sb + (unsigned)ti.w * (kBrickCells * 4u * (unsigned)sizeof(T));
+#pragma unroll
+          for (int r = 0; r < NRAW; ++r) {
+            buffer_raw(rs, lane_off, so, raw[r]);
+            so += sb;
+          }
+          return;
+        }
+      }
+      const int j0 = k0 - (CUB ? 2 : 1);
       int sl = p.slot_base + j0;  // j0 >= -3 (-4 for the cubic)
       sl += sl < 0 ? p.capacity : 0;
       sl += sl < 0 ? p.capacity : 0;
@@ -1040,16 +1076,9 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       return;
     }
 #pragma unroll
-    for (int r = 0; r < NRAW; ++r) {
-      if (ti.z & 1)
-        zero_raw(raw[r]);
-      else
-        load_raw(ring, p, k0 - (CUB ? 2 : 1) + r, ti.w, sc, raw[r]);
-    }
+    for (int r = 0; r < NRAW; ++r) load_raw(ring, p, k0 - (CUB ? 2 : 1) + r, ti.w, sc, raw[r]);
   };
-  auto write_round = [&](int pos, int n) {
-    const int4 ti = slot_entry(pos, n, sj);
-    if (ti.z & 1) return;
+  auto write_round = [&](const int4& ti) {
     const int base = (sj * kBrickCells + sc) * kCellStride + sq * EPT;
     // A history that starts at slice 0: an entry of an earlier slice was
     // staged from the held slice 0 at every node, so all its planes but the
@@ -1105,8 +1134,16 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
     // each round loads its raw slices at its start: holding the next round's
     // in registers while this one computes costs the pair loop more (spills)
     // than the loads' latency
-    load_round(pos, cnt);
-    write_round(pos, cnt);
+    {
+      const int4 tv = slot_entry(pos, cnt, sjw);
+      const int4 ti = make_int4(__builtin_amdgcn_readfirstlane(tv.x), 0, __builtin_amdgcn_readfirstlane(tv.z),
+                                __builtin_amdgcn_readfirstlane(tv.w));
+      // nothing to stage for an empty or dead brick slot
+      if (!(ti.z & 1)) {
+        load_round(ti);
+        write_round(ti);
+      }
+    }
     const int npos = pos + cnt;
     const bool probe = tail - npos < G && cursor < b_end;
     if (probe) refill(pos, tail, cursor);
