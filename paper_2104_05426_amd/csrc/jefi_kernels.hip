@@ -370,16 +370,19 @@ __device__ __forceinline__ void entry_at(const float4* lds, int PU, int e, float
   }
 }
 
-template <bool CUB>
-__device__ __forceinline__ void entry_at(const float4* lds, int PU, int e, double f, double dsc, double v[4],
-                                         double w[4]) {
+// FP64 entries: the eight 16-byte plane reads of entry e, then the value
+// and derivative at fraction f from them (as for FP32).
+__device__ __forceinline__ void planes_at(const float4* lds, int PU, int e, double P[4][4]) {
   const double2* l2 = (const double2*)lds;
-  double P[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const double2 lo = l2[2 * i * PU + e], hi = l2[(2 * i + 1) * PU + e];
     P[i][0] = lo.x; P[i][1] = lo.y; P[i][2] = hi.x; P[i][3] = hi.y;
   }
+}
+
+template <bool CUB>
+__device__ __forceinline__ void entry_from(const double P[4][4], double f, double dsc, double v[4], double w[4]) {
   if constexpr (!CUB) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q] = __builtin_fma(f, P[1][q], P[0][q]);
@@ -398,6 +401,14 @@ __device__ __forceinline__ void entry_at(const float4* lds, int PU, int e, doubl
       w[q] = d2 * dsc;
     }
   }
+}
+
+template <bool CUB>
+__device__ __forceinline__ void entry_at(const float4* lds, int PU, int e, double f, double dsc, double v[4],
+                                         double w[4]) {
+  double P[4][4];
+  planes_at(lds, PU, e, P);
+  entry_from<CUB>(P, f, dsc, v, w);
 }
 
 // Geometry of one observation tile: first/last point indices, the FP64
@@ -848,12 +859,12 @@ __device__ __forceinline__ double rsqrt_f64(double r2) {
   return __builtin_fma(y, e, y);
 }
 
-// Field contribution of one pair from its LDS entry (FP64); ri = 1/R.
+// Field contribution of one pair from the planes of its entry (FP64); ri = 1/R.
 template <bool CUB>
-__device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, double f, double ri, double dx,
-                                            double dy, double dz, double dE[3], double dB[3], double dsc) {
+__device__ __forceinline__ void pair_fields_from(const double P[4][4], double f, double ri, double dx, double dy,
+                                                 double dz, double dE[3], double dB[3], double dsc) {
   double v[4], w[4];
-  entry_at<CUB>(lds, PU, e, f, dsc, v, w);
+  entry_from<CUB>(P, f, dsc, v, w);
   const double rho = v[0], jx = v[1], jy = v[2], jz = v[3];
   const double rhod = w[0], jdx = w[1], jdy = w[2], jdz = w[3];
   const double ri2 = ri * ri;
@@ -874,6 +885,14 @@ __device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, do
   dB[1] = __builtin_fma(-Lx, uz, dB[1]);
   dB[2] = __builtin_fma(Lx, uy, dB[2]);
   dB[2] = __builtin_fma(-Ly, ux, dB[2]);
+}
+
+template <bool CUB>
+__device__ __forceinline__ void pair_fields(const float4* lds, int PU, int e, double f, double ri, double dx,
+                                            double dy, double dz, double dE[3], double dB[3], double dsc) {
+  double P[4][4];
+  planes_at(lds, PU, e, P);
+  pair_fields_from<CUB>(P, f, ri, dx, dy, dz, dE, dB, dsc);
 }
 
 struct FpAcc {
@@ -1361,11 +1380,14 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           // 1e-15 of the canonical value), and it is N iff the canonical r2 is
           // at most the threshold T(N): no correctly rounded square root.
           const int4 ti = tab_i[q];
-          const int off = p.a_i - ti.x;  // window slot of floor position m: m + off
+          // window slot of floor position m: m + off (uniform, so that the clamp
+          // below takes a scalar operand)
+          const int off = __builtin_amdgcn_readfirstlane(p.a_i - ti.x);
           const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
           // below mlo lies the zero entry of pairs wholly before the oldest
-          // slice (only bricks flagged by bit 2 have such pairs)
-          const int mlo = (tz & 4) ? -off : INT_MIN;
+          // slice (only bricks flagged by bit 2 have such pairs); one scalar,
+          // so that each pair's clamp is a single max
+          const int mlo = __builtin_amdgcn_readfirstlane((tz & 4) ? -off : INT_MIN);
           const double* bc = tab_c[q];
           const double ex[2] = {rox - bc[0], rox - bc[1]};
           const double ey[2] = {roy - bc[2], roy - bc[3]};
@@ -1399,16 +1421,31 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) tn[q] = thr_at[nn[q]];
+            if constexpr (FP) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int c = 4 * cz + q;
-              const int mm = r2[q] <= tn[q] ? nn[q] : nn[q] - 1;
-              if (FP) {
-                fpa.add(p.a_i + mm, cell_s(s_base, c));
-                continue;
+              for (int q = 0; q < 4; ++q) {
+                const int mm = r2[q] <= tn[q] ? nn[q] : nn[q] - 1;
+                fpa.add(p.a_i + mm, cell_s(s_base, 4 * cz + q));
               }
-              const int e = cellbase + c * kCellStride + max(mm, mlo);
-              pair_fields<CUB>(lds, PU, e, u[q] - (double)mm, ri[q], ex[q & 1], ey[q >> 1], ez[cz], dE, dB, inv_dt);
+            } else {
+              // the layer's four entries and fractions, then each pair's
+              // planes read after the previous pair's fields are formed
+              // (fewer registers held across the layer)
+              int e[4];
+              double fq[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int mm = r2[q] <= tn[q] ? nn[q] : nn[q] - 1;
+                e[q] = cellbase + (4 * cz + q) * kCellStride + max(mm, mlo);
+                fq[q] = u[q] - (double)mm;
+              }
+              double P[2][4][4];
+              planes_at(lds, PU, e[0], P[0]);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                pair_fields_from<CUB>(P[q & 1], fq[q], ri[q], ex[q & 1], ey[q >> 1], ez[cz], dE, dB, inv_dt);
+                if (q < 3) planes_at(lds, PU, e[q + 1], P[(q + 1) & 1]);
+              }
             }
           }
           continue;
