@@ -1149,6 +1149,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   int row_key = -1;
   float sy0 = 0.f, sy1 = 0.f, sz0 = 0.f, sz1 = 0.f, yzs[4] = {0.f, 0.f, 0.f, 0.f};
   double ey2s[2] = {0.0, 0.0}, ez2s[2] = {0.0, 0.0};
+  // FP64 full bricks: the y and z separations and squares of the last brick row
+  double rey[2] = {0.0, 0.0}, rez[2] = {0.0, 0.0}, ry2[2] = {0.0, 0.0}, rz2[2] = {0.0, 0.0};
   for (bool more = b_begin < b_end; more;) {
     // each round loads its raw slices at its start: holding the next round's
     // in registers while this one computes costs the pair loop more (spills)
@@ -1389,12 +1391,24 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           // so that each pair's clamp is a single max
           const int mlo = __builtin_amdgcn_readfirstlane((tz & 4) ? -off : INT_MIN);
           const double* bc = tab_c[q];
+          const int row = __builtin_amdgcn_readfirstlane(__float_as_int(tab_f[q].w));
+          if (row != row_key) {
+            row_key = row;
+            rey[0] = roy - bc[2];
+            rey[1] = roy - bc[3];
+            rez[0] = roz - bc[4];
+            rez[1] = roz - bc[5];
+            ry2[0] = rey[0] * rey[0];
+            ry2[1] = rey[1] * rey[1];
+            rz2[0] = rez[0] * rez[0];
+            rz2[1] = rez[1] * rez[1];
+          }
           const double ex[2] = {rox - bc[0], rox - bc[1]};
-          const double ey[2] = {roy - bc[2], roy - bc[3]};
-          const double ez[2] = {roz - bc[4], roz - bc[5]};
+          const double* ey = rey;
+          const double* ez = rez;
           const double x2[2] = {ex[0] * ex[0], ex[1] * ex[1]};
-          const double y2[2] = {ey[0] * ey[0], ey[1] * ey[1]};
-          const double z2[2] = {ez[0] * ez[0], ez[1] * ez[1]};
+          const double* y2 = ry2;
+          const double* z2 = rz2;
           if (!FP && (tz & 4) && !(p.stencil & kStencilHold)) {
             // straddling the switch-on front: skip the brick for this
             // wavefront when even its nearest cell lies wholly before slice -1
