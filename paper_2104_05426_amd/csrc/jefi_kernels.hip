@@ -909,6 +909,13 @@ struct FpAcc {
 // Table entries of live bricks waiting for their round (a power of two).
 constexpr int kBrickRing = 64;
 
+// A live brick's table entry: window and flags, and its FP32 corner and
+// row (brick_info), side by side so that one address serves both reads.
+struct BrickEntry {
+  int4 i;
+  float4 f;
+};
+
 // Launch shape: WZ = 1 (8x8x4 tiles, 256 threads) or 2 (8x8x8, 512 threads);
 // W = slots staged per cell (32, 64 or 128) -- the longer the window, the
 // fewer bricks fit a round in the same LDS.
@@ -934,7 +941,7 @@ struct FastShape {
 template <typename T, int WZ, bool FP, int IDX, int W, int STG, class PP>
 __device__ __forceinline__ void pair_body(const PP& p, int bid,
                                           float4 (&lds)[FastShape<T, WZ, W>::NPL * FastShape<T, WZ, W>::PU],
-                                          int4 (&tab_i)[kBrickRing], float4 (&tab_f)[kBrickRing],
+                                          BrickEntry (&tab)[kBrickRing],
                                           double (&tab_c)[kBrickRing][6],
                                           double (&thr)[FastShape<T, WZ, W>::THR], int (&qs)[2]) {
   using Raw = typename RawOf<T>::type;
@@ -1013,8 +1020,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       const int take = min(got, kBrickRing - (tail - keep));
       if (live && rank < take) {
         const int q = (tail + rank) & (kBrickRing - 1);
-        tab_i[q] = ti;
-        tab_f[q] = tf;
+        tab[q].i = ti;
+        tab[q].f = tf;
         for (int k = 0; k < 6; ++k) tab_c[q][k] = cc[k];
       }
       const unsigned long long last = __ballot(live && rank == take - 1);
@@ -1026,7 +1033,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
   };
   // the round's brick slot j: entry pos + j when j < n, else a dead entry
   auto slot_entry = [&](int pos, int n, int j) {
-    return j < n ? tab_i[(pos + j) & (kBrickRing - 1)] : make_int4(0, -1, 1, 0);
+    return j < n ? tab[(pos + j) & (kBrickRing - 1)].i : make_int4(0, -1, 1, 0);
   };
   // The 64 threads of a wavefront stage one brick slot (NQ is a multiple of
   // 8, so t >> 3 stays within one sj): the slot's table entry, its ring
@@ -1186,7 +1193,8 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
 #pragma unroll 1
       for (int j = 0; j < cnt; ++j) {
         const int q = (pos + j) & (kBrickRing - 1);
-        const int tz = __builtin_amdgcn_readfirstlane(tab_i[q].z);
+        const BrickEntry be = tab[q];
+        const int tz = __builtin_amdgcn_readfirstlane(be.i.z);
         if (tz & 1) {
           if (FP && (tz & 2)) slow |= 1u << j;  // fingerprint: count its screened pairs
           continue;
@@ -1195,12 +1203,13 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           slow |= 1u << j;
           continue;
         }
-        const int4 ti = tab_i[q];
-        const int off = p.a_i - ti.x;  // window slot of floor position m: m + off
-        const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
+        const int4 ti = be.i;
+        // window slot of floor position m: m + off
+        const int off = __builtin_amdgcn_readfirstlane(p.a_i - ti.x);
+        const int cellbase = j * kBrickCells * kCellStride + off;
         const int mlo = -off;
         const double* bc = tab_c[q];
-        const float4 tf = tab_f[q];
+        const float4 tf = be.f;
         const int row = __builtin_amdgcn_readfirstlane(__float_as_int(tf.w));
         if (row != row_key) {
           row_key = row;
@@ -1327,14 +1336,14 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
       for (int j = 0; slow != 0u; ++j, slow >>= 1) {
         if (!(slow & 1u)) continue;
         const int q = (pos + j) & (kBrickRing - 1);
-        const int4 ti = tab_i[q];
+        const int4 ti = tab[q].i;
         const int lo = ti.x;
         const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;
         const int cellbase = __builtin_amdgcn_readfirstlane(j * kBrickCells * kCellStride + off);
         const int mlo = -off, mhi = hiw - off;
         const double* bc = tab_c[q];
-        const float4 tf = tab_f[q];
+        const float4 tf = tab[q].f;
         const float d0x = xo - tf.x, d0y = yo - tf.y, d0z = zo - tf.z;
         const float d1x = d0x - hsx, d1y = d0y - hsy, d1z = d0z - hsz;
         const int s_base = FP ? brick_s_base(ti.w) : 0;
@@ -1374,14 +1383,14 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
 #pragma unroll 1
       for (int j = 0; j < cnt; ++j) {
         const int q = (pos + j) & (kBrickRing - 1);
-        const int tz = __builtin_amdgcn_readfirstlane(tab_i[q].z);
+        const int tz = __builtin_amdgcn_readfirstlane(tab[q].i.z);
         if ((tz & 1) && !(FP && (tz & 2))) continue;  // fingerprint: dead near bricks still count screening
         if (p.use_thr && (tz & 0xff02) == 0xff00) {
           // A full far brick: every pair's canonical floor position is N or
           // N - 1 for N the integer nearest u (u from a refined 1/sqrt, within
           // 1e-15 of the canonical value), and it is N iff the canonical r2 is
           // at most the threshold T(N): no correctly rounded square root.
-          const int4 ti = tab_i[q];
+          const int4 ti = tab[q].i;
           // window slot of floor position m: m + off (uniform, so that the clamp
           // below takes a scalar operand)
           const int off = __builtin_amdgcn_readfirstlane(p.a_i - ti.x);
@@ -1391,7 +1400,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           // so that each pair's clamp is a single max
           const int mlo = __builtin_amdgcn_readfirstlane((tz & 4) ? -off : INT_MIN);
           const double* bc = tab_c[q];
-          const int row = __builtin_amdgcn_readfirstlane(__float_as_int(tab_f[q].w));
+          const int row = __builtin_amdgcn_readfirstlane(__float_as_int(tab[q].f.w));
           if (row != row_key) {
             row_key = row;
             rey[0] = roy - bc[2];
@@ -1464,7 +1473,7 @@ __device__ __forceinline__ void pair_body(const PP& p, int bid,
           }
           continue;
         }
-        const int4 ti = tab_i[q];
+        const int4 ti = tab[q].i;
         const int lo = ti.x;
         const int hiw = min(ti.y - lo, W - 1);
         const int off = p.a_i - lo;
@@ -1562,12 +1571,11 @@ template <typename T, int WZ, bool FP, int IDX, int W, int STG>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_fast(PairParams p) {
   using S = FastShape<T, WZ, W>;
   __shared__ float4 lds[S::NPL * S::PU];
-  __shared__ int4 tab_i[kBrickRing];
-  __shared__ float4 tab_f[kBrickRing];
+  __shared__ BrickEntry tab[kBrickRing];
   __shared__ double tab_c[kBrickRing][6];
   __shared__ double thr[S::THR];
   __shared__ int qs[2];
-  pair_body<T, WZ, FP, IDX, W, STG>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab_i, tab_f,
+  pair_body<T, WZ, FP, IDX, W, STG>(p, xcd_remap((int)blockIdx.x, p.n_wg, p.n_tiles, p.n_splits), lds, tab,
                                     tab_c, thr, qs);
 }
 
@@ -1578,8 +1586,7 @@ template <typename T, int WZ, int IDX, int STG>
 __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) void pair_kernel_persistent(BatchDevice bd) {
   using S = FastShape<T, WZ, 32>;
   __shared__ float4 lds[S::NPL * S::PU];
-  __shared__ int4 tab_i[kBrickRing];
-  __shared__ float4 tab_f[kBrickRing];
+  __shared__ BrickEntry tab[kBrickRing];
   __shared__ double tab_c[kBrickRing][6];
   __shared__ double thr[S::THR];
   __shared__ int qs[2];
@@ -1597,7 +1604,7 @@ __global__ __launch_bounds__(256 * WZ) __attribute__((amdgpu_waves_per_eu(4))) v
     const int bid = __builtin_amdgcn_readfirstlane(item.y);
     using CP = const __attribute__((address_space(4))) PairParams;
     CP& p = *(CP*)(bd.params + inst);
-    pair_body<T, WZ, false, IDX, 32, STG>(p, bid, lds, tab_i, tab_f, tab_c, thr, qs);
+    pair_body<T, WZ, false, IDX, 32, STG>(p, bid, lds, tab, tab_c, thr, qs);
   }
 }
 
