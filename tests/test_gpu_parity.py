@@ -422,6 +422,49 @@ def test_ring_wraparound_matches_fresh_upload():
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_wrapped_rings_give_identical_fields(prec):
+    """A wavefront stages its raw slices through one scalar offset when they
+    lie in 0..nt-1 in consecutive ring slots, and slot by slot with the wrap
+    otherwise. Rings whose oldest used slice sits at many different slots
+    (capacity nt and nt + 7) give, bit for bit, the fields of a ring that
+    holds just the used slices from slot 0, at the newest time, inside the
+    window and before its start."""
+    import torch
+    import paper_2104_05426_amd as J
+    _gpu()
+    src = centred_grid((10, 8, 6), 0.05)
+    obs = src.shifted_cells(6, -1, 2)  # near and far bricks
+    dt, nt = 0.025, 40
+    blobs = [Blob(0.7, 0.08, (0.02, 0.0, -0.03), (0.4, 0.2, 0.0)), Blob(-0.4, 0.12, (0.1, 0.05, 0.0), (0.0, -0.3, 0.2))]
+    hall = blob_history(src, blobs, nt + 2 * (nt + 7), dt)
+    hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP)
+
+    def fields(h, t):
+        E = torch.empty((3, obs.size), dtype=tdt, device="cuda")
+        B = torch.empty((3, obs.size), dtype=tdt, device="cuda")
+        J.jefi_eval_fields(src, h, dt, nt, obs, t, E, B, opt)
+        torch.cuda.synchronize()
+        return E.cpu().numpy(), B.cpu().numpy()
+
+    checked = 0
+    for cap in (nt, nt + 7):
+        for extra in (0, 1, 5, 13, cap - 1, cap + 3, 2 * cap - 2):
+            total = nt + extra
+            ring_store, ring = J.upload_history(src, hall[:total], hdt, capacity=cap)
+            ref_store, ref = J.upload_history(src, hall[total - nt:total], hdt, newest=total - 1, capacity=nt)
+            for back in (0.0, 7.3, nt - 0.5, nt + 2.0):
+                t = (total - 1 - back) * dt
+                Ew, Bw = fields(ring, t)
+                Er, Br = fields(ref, t)
+                assert np.array_equal(Ew, Er) and np.array_equal(Bw, Br), (prec, cap, extra, back)
+                checked += 1
+            del ring_store, ref_store
+    assert checked == 2 * 7 * 4
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_ring_above_2gib_matches_small_ring(prec):
     """A ring of more than 2 GiB (64-bit staging addresses) gives exactly
     the fields of a ring holding only the used steps (32-bit buffer
