@@ -70,6 +70,58 @@ def test_batch_equals_solo_and_oracle(prec, tile):
     print(f"batch of {len(probs)} ({prec}, tile {tile}) matches solo and oracle", flush=True)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_with_wrapped_rings(prec):
+    """The persistent kernel stages through the same wavefront-uniform ring
+    offsets as a single launch: instances whose rings have wrapped at
+    different slots give, bit for bit, the batch results of rings holding
+    just their used slices."""
+    import torch
+    import paper_2104_05426_amd as J
+    _gpu()
+    rng = np.random.default_rng(57)
+    hdt = J.JEFI_F64 if prec == "f64" else J.JEFI_F32
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    opt = J.jefi_options_default(precision=J.JEFI_PREC_F64 if prec == "f64" else J.JEFI_PREC_F32_COMP)
+    keep, specs = [], []
+    for k in range(8):
+        es = int(rng.integers(6, 17))
+        eo = int(rng.integers(5, 21))
+        dx = 1.6 / es
+        dt = dx / 2.0
+        nt = 2 * es + 8
+        extra = int(rng.integers(0, 3 * nt))
+        cap = nt + 5 * (k % 3)
+        src = centred_grid((es, es, es), dx)
+        m = (es - eo) // 2
+        obs = Grid((eo, eo, eo), tuple(src.origin[a] + m * dx for a in range(3)), (dx, dx, dx))
+        blobs = workloads.draw_blobs(rng, int(rng.integers(1, 6)), (-0.8, 0.8))
+        hall = blob_history(src, blobs, nt + extra, dt)
+        specs.append((src, obs, dt, nt, extra, cap, hall))
+    outs = []
+    for wrapped in (True, False):
+        probs = []
+        res = []
+        for src, obs, dt, nt, extra, cap, hall in specs:
+            newest = nt + extra - 1
+            if wrapped:
+                st, h = J.upload_history(src, hall, hdt, capacity=cap)
+            else:
+                st, h = J.upload_history(src, hall[extra:], hdt, newest=newest, capacity=nt)
+            assert h.newest == newest
+            E = torch.empty((3, obs.size), dtype=tdt, device="cuda")
+            B = torch.empty((3, obs.size), dtype=tdt, device="cuda")
+            keep.append(st)
+            res.append((E, B))
+            probs.append(J.make_problem(src, h, dt, nt, obs, (newest - 0.35) * dt, E, B))
+        J.jefi_eval_batch(probs, opt)
+        torch.cuda.synchronize()
+        outs.append([(E.cpu().numpy(), B.cpu().numpy()) for E, B in res])
+    for k, ((Ew, Bw), (Ef, Bf)) in enumerate(zip(*outs)):
+        assert np.array_equal(Ew, Ef) and np.array_equal(Bw, Bf), (prec, k)
+    assert any(s[4] >= s[5] for s in specs)  # some rings did wrap
+
+
 @pytest.mark.parametrize("flags", [1, 2])
 def test_batch_index_modes(flags):
     """The persistent kernel in both FP32 index modes (guard band; threshold
