@@ -71,6 +71,13 @@ struct MockEvent {
 int g_eval_sleep_us = 0;    // set by the test to keep batches on the "device" longer
 int g_ingest_sleep_us = 0;  // likewise for ring uploads (re-materialisation)
 
+// Batches launched so far, and a gate that keeps the next n batches on their
+// streams until the test releases them, in launch order (scenarios that need
+// a fixed order of completions whatever the threads' timing).
+static std::mutex g_gate_mu;
+static std::condition_variable g_gate_cv;
+static int g_launched = 0, g_gate_base = 0, g_gate_n = 0, g_gate_released = 0;
+
 hipError_t hipSetDevice(int) { return hipSuccess; }
 hipError_t hipGetDevice(int* d) {
   *d = 0;
@@ -191,6 +198,17 @@ std::atomic<unsigned> g_last_batch_flags{0};
 
 jefi_status jefi_eval_batch(const jefi_problem* probs, int32_t n, const jefi_options* opt, void* stream) {
   g_last_batch_flags.store(opt->flags);
+  int held = -1;
+  {
+    std::lock_guard<std::mutex> lk(g_gate_mu);
+    const int idx = g_launched++;
+    if (idx >= g_gate_base && idx < g_gate_base + g_gate_n) held = idx - g_gate_base;
+  }
+  if (held >= 0)
+    ((hipStream_t)stream)->push([held]() {
+      std::unique_lock<std::mutex> lk(g_gate_mu);
+      g_gate_cv.wait(lk, [held]() { return g_gate_released > held; });
+    });
   // the whole batch "runs" for a while before it reads any ring, which
   // leaves room for a later batch to overtake it if nothing orders them
   const int sleep_us = g_eval_sleep_us;
@@ -253,3 +271,21 @@ hipError_t launch_ingest_slots(const void* hist, void* ring, const GridD& src, i
 }  // namespace jefi
 
 int jefi_mock_express_grid() { return jefi::g_express_grid_cus.load(); }
+
+int jefi_mock_batches_launched() {
+  std::lock_guard<std::mutex> lk(g_gate_mu);
+  return g_launched;
+}
+
+void jefi_mock_hold_next_batches(int n) {
+  std::lock_guard<std::mutex> lk(g_gate_mu);
+  g_gate_base = g_launched;
+  g_gate_n = n;
+  g_gate_released = 0;
+}
+
+void jefi_mock_release_batch() {
+  std::lock_guard<std::mutex> lk(g_gate_mu);
+  ++g_gate_released;
+  g_gate_cv.notify_all();
+}

@@ -18,6 +18,9 @@ extern int g_eval_sleep_us;
 extern int g_ingest_sleep_us;
 extern std::atomic<unsigned> g_last_batch_flags;
 int jefi_mock_express_grid();  // grid (compute units) of the last express-lane batch
+int jefi_mock_batches_launched();
+void jefi_mock_hold_next_batches(int n);  // the next n batches wait on their streams ...
+void jefi_mock_release_batch();           // ... until released, one per call, in launch order
 
 static std::atomic<int> g_fail{0};
 #define CHECK(c)                                                \
@@ -357,22 +360,35 @@ void option_flags() {
 //     batch holds A only, and B's (slow) ring upload is queued on its stream;
 //   - when C completes, B's request runs on C's stream.
 // B's result is right only if its push and evaluation follow the upload.
+// G and C are held on their streams until released, so that A and B queue
+// behind them and G completes first whatever the threads' timing.
+void wait_launched(int n) {
+  for (int i = 0; i < 100000 && jefi_mock_batches_launched() < n; ++i)
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  CHECK(jefi_mock_batches_launched() >= n);
+}
+
 void materialised_but_not_admitted() {
   std::vector<char> arena;
   jefi_server* sv = make_server(312000, 2, 64, arena);
-  g_eval_sleep_us = 20000;
+  g_eval_sleep_us = 0;
   g_ingest_sleep_us = 0;
   std::vector<Session> ss = {{51, 10, 0}, {52, 4, 0}, {53, 4, 0}, {54, 4, 0}};  // B A C G
   open_sessions(sv, ss, 3);
   Session &B = ss[0], &A = ss[1], &C = ss[2], &G = ss[3];
   Pending pg, pc, pa, pb;
+  const int base = jefi_mock_batches_launched();
+  jefi_mock_hold_next_batches(2);
   submit(sv, G, pg, 20);  // 8000 points: 192000 B of outputs
-  std::this_thread::sleep_for(std::chrono::milliseconds(8));
+  wait_launched(base + 1);
   submit(sv, C, pc, 15);  // 3375 points: 81152 B
-  std::this_thread::sleep_for(std::chrono::milliseconds(4));
+  wait_launched(base + 2);
   g_ingest_sleep_us = 40000;
   submit(sv, A, pa, 1);
   submit(sv, B, pb, 1);
+  jefi_mock_release_batch();  // G completes: A is admitted, B brought back but not admitted
+  wait_launched(base + 3);
+  jefi_mock_release_batch();  // C completes: B runs on its stream
   check_result(sv, pg);
   check_result(sv, pc);
   check_result(sv, pa);
